@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of the disconnected-loop trace estimator on one MI355X.
+
+Workload (default): 16^3 x 32 lattice, link spread eps = 0.5, m0 = 0.02,
+antiperiodic in time; distance-2 torus colouring of the 4D lattice (16
+colours, sigma = (1,2,3,4)) x time dilution on t0 = 0 x 12-fold spin-colour
+dilution x 4 Rademacher seeds.  One step = one colour batch of 48 right-hand
+sides through the whole hot path: source generation, batched solve to a true
+relative residual of 1e-10 (FP16-storage / FP32-arithmetic BiCGStab inside
+FP64 defect correction), and the gamma5 contraction on t0.  Inputs are
+synthetic and resident in HBM before timing starts.
+
+Reported (one JSON line):
+  value     algorithmic HBM GB/s of the Wilson-Dirac operator kernels over the
+            timed steps (bytes: each input spinor read once, each output
+            written once, links once per launch; time: HIP events on the
+            library's stream around every launch);
+  roofline  the same for the dominant operator kernel against 8 TB/s;
+  seconds per trace (all colour batches) for the mixed path and for the
+  FP64 path on the same lattice, and the oracle timed on this host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(U, m0, dims, b_host, n_rhs):
+    """The oracle's operator (scipy CSR assembled from the definition, then a
+    sparse product) applied to the whole batch, timed on this host."""
+    import numpy as np
+    from oracle import dirac
+    t = time.perf_counter()
+    dirac.apply_D(U, m0, b_host, dims, -1)
+    dt = time.perf_counter() - t
+    V = int(np.prod(dims))
+    alg = V * (n_rhs * 2 * 192 + 4 * 144)
+    return dict(value=alg / dt / 1e9, unit="GB/s", cores=1, kind="oracle",
+                sample=f"one application of the oracle's D (CSR assembly + product) to the "
+                       f"{n_rhs}-RHS FP64 batch on {dims}, {dt:.1f} s; scipy's sparse product "
+                       f"runs on one thread (host has {len(os.sched_getaffinity(0))} cores)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--inner-tol", type=float, default=0.05)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the trace estimate "
+              "shards by colour batch with no communication, see DESIGN.md", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from synth.gauge import gauge_field
+    from synth.workloads import workload
+    from paper_2607_05157_amd import wdt
+
+    cfg = workload("loop_16c32_d2")
+    dims, m0, N, t0 = cfg["dims"], cfg["m0"], cfg["n_rhs"], cfg["t0"]
+    seeds = cfg["noise_seeds"]
+    wdt.init(0)
+    log("gauge field", dims)
+    U = gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
+    lat = wdt.Lattice(dims, cfg["bc_t"])
+    g = wdt.Gauge(lat, U)
+    n_c, sigma = wdt.colouring_search(dims, cfg["colouring_d"])
+    # colours present on the source slice t0 (time dilution keeps only those)
+    Lx, Ly, Lz = dims[:3]
+    xs = np.indices((Lx, Ly, Lz)).reshape(3, -1)
+    present = sorted(set(int(v) for v in (np.array(sigma[:3]) @ xs + sigma[3] * t0) % n_c))
+    G5 = np.diag([1, 1, -1, -1]).astype(complex)
+
+    def descs(j):
+        sd = [s for s in seeds for _ in range(12)]
+        comp = [k for _ in seeds for k in range(12)]
+        return wdt.source_descs(sd, n_c=n_c, colour=j, sigma=sigma, component=comp, t0=t0)
+
+    b = lat.new_batch(N)
+    x = lat.new_batch(N)
+
+    def step(j, prec):
+        wdt.sources(lat, descs(j), b)
+        rc, st = wdt.solve(g, m0, b, x, N, tol=cfg["tol"], prec=prec, inner_tol=args.inner_tol,
+                           max_iter=20000, max_outer=60, check_every=10)
+        loop = wdt.contract(lat, b, x, N, spin=G5)[:, t0]
+        return st, loop
+
+    log("warmup", args.warmup)
+    for w in range(args.warmup):
+        step(present[w % len(present)], wdt.FP16)
+    torch.cuda.synchronize()
+
+    log("timed mixed steps", args.steps)
+    wdt.profile(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    stats = []
+    for k in range(args.steps):
+        st, loop = step(present[k % len(present)], wdt.FP16)
+        stats.append(st)
+    torch.cuda.synchronize()
+    t_mixed = (time.perf_counter() - t_start) / args.steps
+    prof = wdt.profile_read()
+    wdt.profile(False)
+
+    log("fp64 steps", args.fp64_steps)
+    torch.cuda.synchronize()
+    t0_ = time.perf_counter()
+    wdt.profile(True)
+    st64 = []
+    for k in range(args.fp64_steps):
+        st, _ = step(present[k % len(present)], wdt.FP64)
+        st64.append(st)
+    torch.cuda.synchronize()
+    t_fp64 = (time.perf_counter() - t0_) / max(1, args.fp64_steps)
+    prof64 = wdt.profile_read()
+    wdt.profile(False)
+
+    dsl = {k: v for k, v in prof.items() if k.startswith("dslash")}
+    tot_b = sum(v["bytes"] for v in dsl.values())
+    tot_ms = sum(v["ms"] for v in dsl.values())
+    value = tot_b / (tot_ms * 1e-3) / 1e9
+    dom = max(dsl, key=lambda k: dsl[k]["ms"])
+    d = dsl[dom]
+    per_launch_b = d["bytes"] / d["calls"]
+    per_launch_ms = d["ms"] / d["calls"]
+    achieved = per_launch_b / (per_launch_ms * 1e-3) / 1e9
+    d64 = prof64.get("dslash_fp64", None)
+    max_res = max(s["true_residual"] for st in stats for s in st)
+    iters = [s["iterations"] for st in stats for s in st]
+    outer = [s["outer"] for st in stats for s in st]
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(U, m0, dims, b.cpu().numpy(), N)
+
+    out = {
+        "metric": "Dslash HBM GB/s (% peak); mixed vs FP64 GPU seconds per trace at 1e-10 residual",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_mixed * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16-storage/f32-arith operator inside f64 refinement",
+        "data": "synthetic",
+        "config": {"workload": "disconnected loop tr[gamma5 D^-1(t0,t0)], 16^3x32, eps=0.5, "
+                               "m0=0.02, 4D torus colouring d=2 x time dilution x Dil12 x 4 seeds",
+                   "dims": list(dims), "n_rhs_per_batch": N, "n_colours": n_c,
+                   "sigma": list(sigma), "colour_batches_per_trace": len(present),
+                   "tol": cfg["tol"], "inner_tol": args.inner_tol},
+        "pct_of_hbm_peak": round(100 * value / HBM_PEAK_GBPS, 1),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "bytes_per_launch": per_launch_b, "avg_launch_ms": per_launch_ms,
+                     "traffic": None},
+        "seconds_per_trace": {"mixed": round(t_mixed * len(present), 3),
+                              "fp64": round(t_fp64 * len(present), 3),
+                              "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3)},
+        "fp64_dslash_gbps": round(d64["gbps"], 1) if d64 else None,
+        "kernels_mixed": {k: {"calls": v["calls"], "ms": round(v["ms"], 3),
+                              "gbps": round(v["gbps"], 1)} for k, v in prof.items()},
+        "kernels_fp64": {k: {"calls": v["calls"], "ms": round(v["ms"], 3),
+                             "gbps": round(v["gbps"], 1)} for k, v in prof64.items()},
+        "solver": {"max_true_residual": max_res, "iterations_max": max(iters),
+                   "outer_max": max(outer),
+                   "fp64_iterations_max": max(s["iterations"] for st in st64 for s in st)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

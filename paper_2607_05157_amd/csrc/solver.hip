@@ -1,0 +1,563 @@
+// Batched BiCGStab for D x = b (one independent recurrence per right-hand
+// side, Sec. 1: every stochastic sample needs one solve with D), in FP64 or
+// as an FP64 defect-correction loop around an FP32-arithmetic inner solve
+// whose vectors are stored in FP32 or FP16 (with a per-site-per-RHS scale).
+//
+// Per iteration the vector work is:
+//   v = D p                 (operator, fused rhat^dag v)
+//   s = r - alpha v
+//   t = D s                 (operator, fused t^dag s and ||t||^2)
+//   x += alpha p + omega s,  r = s - omega t   (fused rhat^dag r, ||r||^2)
+//   p = r + beta (p - omega v)
+// Per-RHS scalars live on the device; small reduction kernels turn the
+// per-block dot partials into alpha, omega, beta and the convergence flags, so
+// the host only polls the flags every `check_every` iterations.  All sums use
+// a fixed order, so results are bit-reproducible run to run.
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace wdt {
+
+struct RhsState {
+    double2 rho, alpha, omega, beta;
+    double rr, bb, tol2;
+    int active;  // 1 while the RHS is iterating
+    int flag;    // 0 running, 1 converged, 2 breakdown
+    int iters;
+    int pad;
+};
+
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__device__ __forceinline__ double2 cmuld(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Sum partials[(d*G + i)*N + r] over i in a fixed order (one block per RHS).
+__device__ double2 block_sum(const double2 *__restrict__ partials, int d, int G, int N, int r) {
+    __shared__ double2 sm[256];
+    double2 acc = make_double2(0, 0);
+    for (int i = threadIdx.x; i < G; i += blockDim.x) {
+        const double2 p = partials[((size_t)d * G + i) * N + r];
+        acc.x += p.x;
+        acc.y += p.y;
+    }
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sm[threadIdx.x].x += sm[threadIdx.x + w].x;
+            sm[threadIdx.x].y += sm[threadIdx.x + w].y;
+        }
+        __syncthreads();
+    }
+    const double2 out = sm[0];
+    __syncthreads();
+    return out;
+}
+
+// After r = b - D x: rr = ||r||^2, bb = ||b||^2; start the recurrence with
+// rhat = r.  `bb_ref` (optional) supplies the norm the tolerance refers to.
+__global__ void k_init_state(RhsState *st, const double2 *partials, int G, int N, double tol,
+                             const int *mask) {
+    const int r = blockIdx.x;
+    const double2 rr = block_sum(partials, 0, G, N, r);
+    const double2 bb = block_sum(partials, 1, G, N, r);
+    if (threadIdx.x == 0) {
+        RhsState s = st[r];
+        s.rr = rr.x;
+        s.bb = bb.x;
+        s.tol2 = tol * tol;
+        s.rho = make_double2(rr.x, 0.0);
+        s.alpha = make_double2(0, 0);
+        s.omega = make_double2(0, 0);
+        s.beta = make_double2(0, 0);
+        const bool want = (mask == nullptr) || mask[r];
+        const bool done = !(rr.x > s.tol2 * bb.x);
+        s.active = (want && !done) ? 1 : 0;
+        s.flag = done ? 1 : 0;
+        st[r] = s;
+    }
+}
+
+__global__ void k_scalar_alpha(RhsState *st, const double2 *partials, int G, int N) {
+    const int r = blockIdx.x;
+    const double2 rv = block_sum(partials, 0, G, N, r);
+    if (threadIdx.x == 0) {
+        RhsState s = st[r];
+        if (s.active) {
+            if (rv.x == 0.0 && rv.y == 0.0) {
+                s.active = 0;
+                s.flag = 2;
+                s.alpha = make_double2(0, 0);
+            } else {
+                s.alpha = cdiv(s.rho, rv);
+            }
+        } else {
+            s.alpha = make_double2(0, 0);
+        }
+        st[r] = s;
+    }
+}
+
+__global__ void k_scalar_omega(RhsState *st, const double2 *partials, int G, int N) {
+    const int r = blockIdx.x;
+    const double2 ts = block_sum(partials, 0, G, N, r);
+    const double2 tt = block_sum(partials, 1, G, N, r);
+    if (threadIdx.x == 0) {
+        RhsState s = st[r];
+        if (s.active && tt.x > 0.0) {
+            s.omega = make_double2(ts.x / tt.x, ts.y / tt.x);
+        } else {
+            s.omega = make_double2(0, 0);
+        }
+        st[r] = s;
+    }
+}
+
+__global__ void k_scalar_beta(RhsState *st, const double2 *partials, int G, int N) {
+    const int r = blockIdx.x;
+    const double2 rho_new = block_sum(partials, 0, G, N, r);
+    const double2 rr = block_sum(partials, 1, G, N, r);
+    if (threadIdx.x == 0) {
+        RhsState s = st[r];
+        if (s.active) {
+            s.iters += 1;
+            s.rr = rr.x;
+            if (!(rr.x > s.tol2 * s.bb)) {
+                s.active = 0;
+                s.flag = 1;
+                s.beta = make_double2(0, 0);
+            } else if ((rho_new.x == 0.0 && rho_new.y == 0.0) ||
+                       (s.omega.x == 0.0 && s.omega.y == 0.0) || !isfinite(rr.x)) {
+                s.active = 0;
+                s.flag = 2;
+                s.beta = make_double2(0, 0);
+            } else {
+                s.beta = cmuld(cdiv(rho_new, s.rho), cdiv(s.alpha, s.omega));
+                s.rho = rho_new;
+            }
+        } else {
+            s.beta = make_double2(0, 0);
+        }
+        st[r] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernels over (site, rhs) with the operator's block shape.
+
+template <class S> using Rl = typename S::real;
+
+template <class S>
+__device__ __forceinline__ cplx<Rl<S>> to_c(double2 a) {
+    return {(Rl<S>)a.x, (Rl<S>)a.y};
+}
+
+
+
+// s = r - alpha v
+template <class S>
+__global__ __launch_bounds__(256) void k_update_s(int V, int N, int NT, int SB, int chunk,
+                                                  const RhsState *__restrict__ st, SpinorPtr<S> rv,
+                                                  SpinorPtr<S> vv, SpinorPtr<S> sv) {
+    using R = Rl<S>;
+    SITE_LOOP_BEGIN
+    const cplx<R> a = to_c<S>(st[r].alpha);
+    cplx<R> x[12], y[12];
+    load_site<S>(rv, s, r, x);
+    load_site<S>(vv, s, r, y);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) x[k] = csub(x[k], cmul(a, y[k]));
+    store_site<S>(sv, s, r, x);
+    SITE_LOOP_END
+}
+
+// x += alpha p + omega s;  r = s - omega t;  partials: rhat^dag r, ||r||^2
+template <class S>
+__global__ __launch_bounds__(256) void k_update_xr(int V, int N, int NT, int SB, int chunk,
+                                                   const RhsState *__restrict__ st, SpinorPtr<S> xv,
+                                                   SpinorPtr<S> pv, SpinorPtr<S> sv,
+                                                   SpinorPtr<S> tv, SpinorPtr<S> rv,
+                                                   SpinorPtr<S> rhat, double2 *partials) {
+    using R = Rl<S>;
+    __shared__ double2 red[2][256];
+    double d0r = 0, d0i = 0, d1r = 0;
+    SITE_LOOP_BEGIN
+    const cplx<R> a = to_c<S>(st[r].alpha);
+    const cplx<R> w = to_c<S>(st[r].omega);
+    cplx<R> x[12], p[12], sv_[12], t[12], h[12];
+    load_site<S>(xv, s, r, x);
+    load_site<S>(pv, s, r, p);
+    load_site<S>(sv, s, r, sv_);
+    load_site<S>(tv, s, r, t);
+    load_site<S>(rhat, s, r, h);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        x[k] = cadd(x[k], cadd(cmul(a, p[k]), cmul(w, sv_[k])));
+        p[k] = csub(sv_[k], cmul(w, t[k]));  // new r
+        d0r += (double)h[k].re * p[k].re + (double)h[k].im * p[k].im;
+        d0i += (double)h[k].re * p[k].im - (double)h[k].im * p[k].re;
+        d1r += (double)p[k].re * p[k].re + (double)p[k].im * p[k].im;
+    }
+    store_site<S>(xv, s, r, x);
+    store_site<S>(rv, s, r, p);
+    SITE_LOOP_END
+    red[0][tid] = make_double2(d0r, d0i);
+    red[1][tid] = make_double2(d1r, 0.0);
+    __syncthreads();
+    if (ry == 0 && r < N) {
+        double2 s0 = red[0][rl], s1 = red[1][rl];
+        for (int y = 1; y < SB; ++y) {
+            s0.x += red[0][y * NT + rl].x;
+            s0.y += red[0][y * NT + rl].y;
+            s1.x += red[1][y * NT + rl].x;
+        }
+        partials[((size_t)0 * gridDim.x + Lb) * N + r] = s0;
+        partials[((size_t)1 * gridDim.x + Lb) * N + r] = s1;
+    }
+}
+
+// p = r + beta (p - omega v)
+template <class S>
+__global__ __launch_bounds__(256) void k_update_p(int V, int N, int NT, int SB, int chunk,
+                                                  const RhsState *__restrict__ st, SpinorPtr<S> rv,
+                                                  SpinorPtr<S> pv, SpinorPtr<S> vv) {
+    using R = Rl<S>;
+    SITE_LOOP_BEGIN
+    const cplx<R> b = to_c<S>(st[r].beta);
+    const cplx<R> w = to_c<S>(st[r].omega);
+    cplx<R> x[12], p[12], v[12];
+    load_site<S>(rv, s, r, x);
+    load_site<S>(pv, s, r, p);
+    load_site<S>(vv, s, r, v);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) p[k] = cadd(x[k], cmul(b, csub(p[k], cmul(w, v[k]))));
+    store_site<S>(pv, s, r, p);
+    SITE_LOOP_END
+}
+
+// dst(T) = src(S) converted (and optionally dst += src when ADD)
+template <class SS, class SD, bool ADD>
+__global__ __launch_bounds__(256) void k_convert(int V, int N, int NT, int SB, int chunk,
+                                                 SpinorPtr<SS> src, SpinorPtr<SD> dst) {
+    SITE_LOOP_BEGIN
+    cplx<Rl<SS>> a[12];
+    load_site<SS>(src, s, r, a);
+    cplx<Rl<SD>> b[12];
+    if constexpr (ADD) {
+        load_site<SD>(dst, s, r, b);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            b[k].re += (Rl<SD>)a[k].re;
+            b[k].im += (Rl<SD>)a[k].im;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) b[k] = {(Rl<SD>)a[k].re, (Rl<SD>)a[k].im};
+    }
+    store_site<SD>(dst, s, r, b);
+    SITE_LOOP_END
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+
+Shape site_shape(int64_t V, int N) {
+    Shape sh;
+    const int NT = N < 256 ? N : 256;
+    int SB = std::max(1, 256 / NT);
+    // prefer full wavefronts: largest SB <= 256/NT with NT*SB a multiple of 64
+    for (int sb = SB; sb >= 1; --sb)
+        if ((NT * sb) % 64 == 0) {
+            SB = sb;
+            break;
+        }
+    sh.SB = SB;
+    sh.threads = ((NT * SB + 63) / 64) * 64;
+    const int64_t ngroups = (V + SB - 1) / SB;
+    const int64_t Gmax = 2048;
+    int64_t G = std::min<int64_t>(ngroups, Gmax);
+    int64_t chunk = (ngroups + G - 1) / G;
+    G = (ngroups + chunk - 1) / chunk;
+    if (G >= 8) G = ((G + 7) / 8) * 8;  // XCD-aware renumbering needs a multiple of 8
+    sh.G = (int)G;
+    sh.chunk = (int)chunk;
+    return sh;
+}
+
+namespace {
+
+struct SolveWs {
+    RhsState *st;
+    double2 *partials;
+    void *vec[8];
+};
+
+template <class S>
+SpinorPtr<S> sp(void *p, int V, int N) {
+    return make_spinor<S>(p, V, N);
+}
+
+int ensure_ws(wdt_gauge_s *g, size_t bytes) {
+    if (g->ws.bytes >= bytes) return WDT_OK;
+    if (g->ws.ptr) WDT_HIP(hipFree(g->ws.ptr));
+    g->ws.ptr = nullptr;
+    g->ws.bytes = 0;
+    hipError_t e = hipMalloc(&g->ws.ptr, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(WDT_ENOMEM, "workspace allocation of %zu bytes failed", bytes);
+    }
+    g->ws.bytes = bytes;
+    return WDT_OK;
+}
+
+struct Bicg {
+    wdt_gauge_s *g;
+    double m0;
+    int N, V;
+    Shape sh;
+    int NT;
+    dim3 grid;
+    hipStream_t stream;
+    RhsState *st;
+    double2 *part;
+};
+
+// Runs BiCGStab iterations in storage S until every RHS is inactive or
+// `max_iter` is reached.  x, r, rhat, p, v, s, t are S-format vectors; the
+// state must have been initialised (rho, active, tolerances).
+template <class S>
+int bicgstab_iterate(Bicg &B, int prec, void *x, void *r, void *rhat, void *p, void *v, void *s,
+                     void *t, int max_iter, int check_every, std::vector<RhsState> &host_st,
+                     int *iters_done) {
+    const int V = B.V, N = B.N;
+    const Shape &sh = B.sh;
+    int it = 0;
+    // p = r
+    WDT_HIP(hipMemcpyAsync(p, r, spinor_bytes(V, N, prec), hipMemcpyDeviceToDevice, B.stream));
+    const double vb = (double)V * N * site_bytes(prec);  // one vector pass
+    static const char *nm_s[3] = {"axpy_s_fp64", "axpy_s_fp32", "axpy_s_fp16"};
+    static const char *nm_xr[3] = {"update_xr_fp64", "update_xr_fp32", "update_xr_fp16"};
+    static const char *nm_p[3] = {"update_p_fp64", "update_p_fp32", "update_p_fp16"};
+    while (it < max_iter) {
+        WDT_TRY(launch_dslash(B.g, B.m0, prec, 0, EPI_DOT_AUX, p, v, rhat, N, B.part, sh, B.stream));
+        hipLaunchKernelGGL(k_scalar_alpha, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.G, N);
+        {
+            ProfScope pr(nm_s[prec], 3 * vb, B.stream);
+            hipLaunchKernelGGL((k_update_s<S>), B.grid, dim3(sh.threads), 0, B.stream, V, N, B.NT,
+                               sh.SB, sh.chunk, B.st, sp<S>(r, V, N), sp<S>(v, V, N),
+                               sp<S>(s, V, N));
+        }
+        WDT_TRY(launch_dslash(B.g, B.m0, prec, 0, EPI_DOT_TS, s, t, nullptr, N, B.part, sh, B.stream));
+        hipLaunchKernelGGL(k_scalar_omega, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.G, N);
+        {
+            ProfScope pr(nm_xr[prec], 7 * vb, B.stream);
+            hipLaunchKernelGGL((k_update_xr<S>), B.grid, dim3(sh.threads), 0, B.stream, V, N, B.NT,
+                               sh.SB, sh.chunk, B.st, sp<S>(x, V, N), sp<S>(p, V, N),
+                               sp<S>(s, V, N), sp<S>(t, V, N), sp<S>(r, V, N), sp<S>(rhat, V, N),
+                               B.part);
+        }
+        hipLaunchKernelGGL(k_scalar_beta, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.G, N);
+        {
+            ProfScope pr(nm_p[prec], 4 * vb, B.stream);
+            hipLaunchKernelGGL((k_update_p<S>), B.grid, dim3(sh.threads), 0, B.stream, V, N, B.NT,
+                               sh.SB, sh.chunk, B.st, sp<S>(r, V, N), sp<S>(p, V, N),
+                               sp<S>(v, V, N));
+        }
+        WDT_HIP(hipGetLastError());
+        ++it;
+        if (it % check_every == 0 || it == max_iter) {
+            WDT_HIP(hipMemcpyAsync(host_st.data(), B.st, sizeof(RhsState) * N,
+                                   hipMemcpyDeviceToHost, B.stream));
+            WDT_HIP(hipStreamSynchronize(B.stream));
+            bool any = false;
+            for (int k = 0; k < N; ++k) any = any || host_st[k].active;
+            if (!any) break;
+        }
+    }
+    *iters_done = it;
+    return WDT_OK;
+}
+
+}  // namespace
+
+// FP64 solve with reliable restarts on the true residual.
+static int solve_fp64(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
+                      const wdt_solve_params &P, wdt_rhs_stats *stats, hipStream_t stream) {
+    const int V = (int)g->lat.V;
+    const Shape sh = site_shape(V, N);
+    const int NT = N < 256 ? N : 256;
+    const size_t vb = spinor_bytes(V, N, WDT_FP64);
+    const size_t part_bytes = (size_t)2 * sh.G * N * sizeof(double2);
+    const size_t st_bytes = ((sizeof(RhsState) * N + 255) / 256) * 256;
+    const size_t part_off = 6 * vb;
+    const size_t st_off = part_off + ((part_bytes + 255) / 256) * 256;
+    WDT_TRY(ensure_ws(g, st_off + st_bytes));
+    char *base = (char *)g->ws.ptr;
+    void *r = base, *rhat = base + vb, *p = base + 2 * vb, *v = base + 3 * vb, *s = base + 4 * vb,
+         *t = base + 5 * vb;
+    Bicg B{g, m0, N, V, sh, NT, dim3(sh.G, (N + NT - 1) / NT), stream,
+           (RhsState *)(base + st_off), (double2 *)(base + part_off)};
+    WDT_HIP(hipMemsetAsync(B.st, 0, sizeof(RhsState) * N, stream));
+    if (!P.x0_is_guess) WDT_HIP(hipMemsetAsync(x, 0, vb, stream));
+    std::vector<RhsState> hs(N);
+    std::vector<int> total_it(N, 0), restarts(N, 0);
+    const int check = P.check_every > 0 ? P.check_every : 5;
+    int budget = P.max_iter;
+    int rc = WDT_OK;
+    for (int round = 0;; ++round) {
+        // r = b - D x (true residual), rhat = r
+        WDT_TRY(launch_dslash(g, m0, WDT_FP64, 0, EPI_RESID, x, r, b, N, B.part, sh, stream));
+        hipLaunchKernelGGL(k_init_state, dim3(N), dim3(256), 0, stream, B.st, B.part, sh.G, N,
+                           P.tol, (const int *)nullptr);
+        WDT_HIP(hipMemcpyAsync(rhat, r, vb, hipMemcpyDeviceToDevice, stream));
+        WDT_HIP(hipMemcpyAsync(hs.data(), B.st, sizeof(RhsState) * N, hipMemcpyDeviceToHost, stream));
+        WDT_HIP(hipStreamSynchronize(stream));
+        bool any = false;
+        for (int k = 0; k < N; ++k) any = any || hs[k].active;
+        if (!any || budget <= 0 || round > 50) {
+            for (int k = 0; k < N; ++k) {
+                if (stats) {
+                    stats[k].iterations = total_it[k];
+                    stats[k].outer = 0;
+                    stats[k].converged = hs[k].active ? 0 : 1;
+                    stats[k].restarts = restarts[k];
+                    stats[k].true_residual = hs[k].bb > 0 ? std::sqrt(hs[k].rr / hs[k].bb) : 0.0;
+                }
+                if (hs[k].active) rc = WDT_WNOTCONVERGED;
+            }
+            return rc;
+        }
+        for (int k = 0; k < N; ++k)
+            if (hs[k].active && round > 0) restarts[k] += 1;
+        // iteration counters restart from 0 in the state; accumulate host side
+        std::vector<int> before(N);
+        for (int k = 0; k < N; ++k) before[k] = hs[k].iters;
+        int done = 0;
+        WDT_TRY(bicgstab_iterate<F64>(B, WDT_FP64, x, r, rhat, p, v, s, t, budget, check, hs, &done));
+        WDT_HIP(hipMemcpyAsync(hs.data(), B.st, sizeof(RhsState) * N, hipMemcpyDeviceToHost, stream));
+        WDT_HIP(hipStreamSynchronize(stream));
+        for (int k = 0; k < N; ++k) total_it[k] += hs[k].iters - before[k];
+        budget -= done;
+    }
+}
+
+// FP64 defect correction around an inner solve in storage S (F32 or F16).
+template <class S>
+static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N, int prec,
+                       const wdt_solve_params &P, wdt_rhs_stats *stats, hipStream_t stream) {
+    const int V = (int)g->lat.V;
+    const Shape sh = site_shape(V, N);
+    const int NT = N < 256 ? N : 256;
+    const size_t vb64 = spinor_bytes(V, N, WDT_FP64);
+    const size_t vbl = ((spinor_bytes(V, N, prec) + 255) / 256) * 256;
+    const size_t part_bytes = (size_t)2 * sh.G * N * sizeof(double2);
+    const size_t st_bytes = ((sizeof(RhsState) * N + 255) / 256) * 256;
+    const size_t low_off = vb64;
+    const size_t part_off = low_off + 7 * vbl;
+    const size_t st_off = part_off + ((part_bytes + 255) / 256) * 256;
+    const size_t mask_off = st_off + st_bytes;
+    WDT_TRY(ensure_ws(g, mask_off + ((sizeof(int) * N + 255) / 256) * 256));
+    char *base = (char *)g->ws.ptr;
+    void *r64 = base;
+    void *lo[7];
+    for (int i = 0; i < 7; ++i) lo[i] = base + low_off + i * vbl;
+    void *rS = lo[0], *rhat = lo[1], *p = lo[2], *v = lo[3], *s = lo[4], *t = lo[5], *e = lo[6];
+    int *mask = (int *)(base + mask_off);
+    Bicg B{g, m0, N, V, sh, NT, dim3(sh.G, (N + NT - 1) / NT), stream,
+           (RhsState *)(base + st_off), (double2 *)(base + part_off)};
+    const dim3 grid(sh.G, (N + NT - 1) / NT);
+    if (!P.x0_is_guess) WDT_HIP(hipMemsetAsync(x, 0, vb64, stream));
+    std::vector<RhsState> hs(N);
+    std::vector<int> hmask(N);
+    std::vector<int> total_it(N, 0), outer(N, 0);
+    const int check = P.check_every > 0 ? P.check_every : 5;
+    const double inner_tol = P.inner_tol > 0 ? P.inner_tol : 1e-2;
+    const int max_outer = P.max_outer > 0 ? P.max_outer : 30;
+    int budget = P.max_iter;
+    int rc = WDT_OK;
+    WDT_HIP(hipMemsetAsync(B.st, 0, sizeof(RhsState) * N, stream));
+    for (int o = 0;; ++o) {
+        // FP64 true residual r64 = b - D x
+        WDT_TRY(launch_dslash(g, m0, WDT_FP64, 0, EPI_RESID, x, r64, b, N, B.part, sh, stream));
+        hipLaunchKernelGGL(k_init_state, dim3(N), dim3(256), 0, stream, B.st, B.part, sh.G, N,
+                           P.tol, (const int *)nullptr);
+        WDT_HIP(hipMemcpyAsync(hs.data(), B.st, sizeof(RhsState) * N, hipMemcpyDeviceToHost, stream));
+        WDT_HIP(hipStreamSynchronize(stream));
+        bool any = false;
+        for (int k = 0; k < N; ++k) {
+            hmask[k] = hs[k].active;
+            any = any || hs[k].active;
+        }
+        if (!any || o >= max_outer || budget <= 0) {
+            for (int k = 0; k < N; ++k) {
+                if (stats) {
+                    stats[k].iterations = total_it[k];
+                    stats[k].outer = outer[k];
+                    stats[k].converged = hs[k].active ? 0 : 1;
+                    stats[k].restarts = 0;
+                    stats[k].true_residual = hs[k].bb > 0 ? std::sqrt(hs[k].rr / hs[k].bb) : 0.0;
+                }
+                if (hs[k].active) rc = WDT_WNOTCONVERGED;
+            }
+            return rc;
+        }
+        for (int k = 0; k < N; ++k) outer[k] += hmask[k];
+        WDT_HIP(hipMemcpyAsync(mask, hmask.data(), sizeof(int) * N, hipMemcpyHostToDevice, stream));
+        // inner system D e = r (low precision), e = 0, rhat = r
+        hipLaunchKernelGGL((k_convert<F64, S, false>), grid, dim3(sh.threads), 0, stream, V, N, NT,
+                           sh.SB, sh.chunk, sp<F64>(r64, V, N), sp<S>(rS, V, N));
+        WDT_HIP(hipMemsetAsync(e, 0, vbl, stream));
+        // ||r||^2 in the stored precision: residual of e = 0 against rS
+        WDT_TRY(launch_dslash(g, m0, prec, 0, EPI_RESID, e, rhat, rS, N, B.part, sh, stream));
+        hipLaunchKernelGGL(k_init_state, dim3(N), dim3(256), 0, stream, B.st, B.part, sh.G, N,
+                           inner_tol, (const int *)mask);
+        WDT_HIP(hipMemcpyAsync(rS, rhat, spinor_bytes(V, N, prec), hipMemcpyDeviceToDevice, stream));
+        std::vector<int> before(N);
+        WDT_HIP(hipMemcpyAsync(hs.data(), B.st, sizeof(RhsState) * N, hipMemcpyDeviceToHost, stream));
+        WDT_HIP(hipStreamSynchronize(stream));
+        for (int k = 0; k < N; ++k) before[k] = hs[k].iters;
+        int done = 0;
+        WDT_TRY(bicgstab_iterate<S>(B, prec, e, rS, rhat, p, v, s, t, budget, check, hs, &done));
+        WDT_HIP(hipMemcpyAsync(hs.data(), B.st, sizeof(RhsState) * N, hipMemcpyDeviceToHost, stream));
+        WDT_HIP(hipStreamSynchronize(stream));
+        for (int k = 0; k < N; ++k) total_it[k] += hs[k].iters - before[k];
+        budget -= done;
+        // x += e
+        hipLaunchKernelGGL((k_convert<S, F64, true>), grid, dim3(sh.threads), 0, stream, V, N, NT,
+                           sh.SB, sh.chunk, sp<S>(e, V, N), sp<F64>(x, V, N));
+        WDT_HIP(hipGetLastError());
+    }
+    (void)rc;
+}
+
+}  // namespace wdt
+
+extern "C" int wdt_solve(wdt_gauge g, double m0, const void *dev_b, void *dev_x, int32_t n_rhs,
+                         const wdt_solve_params *params, wdt_rhs_stats *stats, void *stream) {
+    using namespace wdt;
+    WDT_CHECK(g != nullptr, "wdt_solve: null gauge handle");
+    WDT_CHECK(dev_b != nullptr && dev_x != nullptr, "wdt_solve: null vector");
+    WDT_CHECK(dev_b != dev_x, "wdt_solve: b and x must not overlap");
+    WDT_CHECK(params != nullptr, "wdt_solve: null params");
+    WDT_CHECK(n_rhs >= 1, "wdt_solve: n_rhs must be >= 1");
+    WDT_CHECK(params->tol > 0 && params->tol < 1, "wdt_solve: tol must be in (0, 1)");
+    WDT_CHECK(params->max_iter >= 1, "wdt_solve: max_iter must be >= 1");
+    const hipStream_t st = (hipStream_t)stream;
+    switch (params->prec) {
+        case WDT_FP64:
+            return solve_fp64(g, m0, dev_b, dev_x, n_rhs, *params, stats, st);
+        case WDT_FP32:
+            return solve_mixed<F32>(g, m0, dev_b, dev_x, n_rhs, WDT_FP32, *params, stats, st);
+        case WDT_FP16:
+            return solve_mixed<F16>(g, m0, dev_b, dev_x, n_rhs, WDT_FP16, *params, stats, st);
+        default:
+            return set_error(WDT_EINVAL, "wdt_solve: bad precision %d", params->prec);
+    }
+}

@@ -1,0 +1,316 @@
+"""GPU parity of the HIP path against the oracle, through the C interface.
+
+Bars: integer / sign work bit-exact (sources, colourings); FP64 operator
+within 1e-14 relative per element (rounding-order differences only); FP64
+traces within relative 1e-10 of the dense-LU oracle; mixed-precision traces
+within 1e-8 after refinement to a relative residual of 1e-10.
+"""
+import numpy as np
+import pytest
+
+from oracle import colouring, dirac, estimator, force as oforce, gamma, noise, solve as osolve
+from synth.gauge import gauge_field
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+W = None
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    global W
+    from paper_2607_05157_amd import wdt
+    W = wdt
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    wdt.init(0)
+    yield
+
+
+def to_dev(a):
+    """numpy [V, 12, N] complex -> device tensor in the library layout."""
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).cuda()
+
+
+def rand_batch(V, N, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((V, 12, N)) + 1j * rng.standard_normal((V, 12, N))
+
+
+# ---------------------------------------------------------------------------
+# sources: bit-exact
+
+@pytest.mark.parametrize("dims,N", [((4, 4, 4, 4), 5), ((6, 4, 2, 6), 48), ((4, 4, 4, 8), 300)])
+def test_sources_bit_exact(dims, N):
+    say("sources", dims, N)
+    lat = W.Lattice(dims, -1)
+    nc, sig = colouring.search(dims, 2)
+    col = colouring.colours(dims, sig, nc)
+    seeds = [(7 * i) % 13 for i in range(N)]
+    kinds = []
+    for i in range(N):
+        kinds.append(dict(colour=i % nc, component=(i % 13) - 1, t0=(i % 3) - 1))
+    descs = W.source_descs(seeds, n_c=nc, colour=[k["colour"] for k in kinds], sigma=sig,
+                           component=[None if k["component"] < 0 else k["component"] for k in kinds],
+                           t0=[k["t0"] for k in kinds])
+    out = lat.new_batch(N)
+    W.sources(lat, descs, out)
+    got = out.cpu().numpy()
+    for i in range(N):
+        k = kinds[i]
+        v = noise.probing_vector(dims, seeds[i], col, k["colour"], k["component"], k["t0"])
+        assert np.array_equal(got[:, :, i], v.astype(np.complex128)), i
+    # plain Rademacher (no masks)
+    descs = W.source_descs(list(range(N)))
+    W.sources(lat, descs, out)
+    got = out.cpu().numpy()
+    for i in range(N):
+        assert np.array_equal(got[:, :, i].real.ravel(), noise.rademacher(i, 12 * lat.V))
+    assert np.all(got.imag == 0)
+
+
+# ---------------------------------------------------------------------------
+# operator
+
+@pytest.mark.parametrize("dims,N,eps,dagger", [((4, 4, 4, 4), 1, 0.3, False),
+                                              ((4, 4, 4, 4), 3, 0.3, True),
+                                              ((6, 2, 4, 6), 48, 0.5, False),
+                                              ((6, 2, 4, 6), 48, 0.5, True),
+                                              ((4, 4, 2, 8), 70, 0.6, False),
+                                              ((2, 2, 2, 2), 5, 0.9, False),
+                                              ((4, 4, 4, 4), 64, 0.0, False)])
+def test_apply_D_fp64(dims, N, eps, dagger):
+    say("apply_D fp64", dims, N, eps, dagger)
+    V = int(np.prod(dims))
+    U = gauge_field(dims, eps, seed=3)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    psi = rand_batch(V, N, 1)
+    out = lat.new_batch(N)
+    W.apply_D(g, 0.1, to_dev(psi), out, N, W.FP64, dagger)
+    torch.cuda.synchronize()
+    ref = dirac.apply_D(U, 0.1, psi, dims, -1, dagger=dagger)
+    err = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    assert err < 1e-14, err
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-6), ("fp16", 4e-3)])
+def test_apply_D_low_precision(prec, tol):
+    dims, N = (4, 4, 2, 6), 48
+    say("apply_D", prec, dims, N)
+    V = int(np.prod(dims))
+    U = gauge_field(dims, 0.5, seed=4)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    psi = rand_batch(V, N, 2)
+    ref = dirac.apply_D(U, 0.05, psi, dims, -1)
+    p = W.FP32 if prec == "fp32" else W.FP16
+    if p == W.FP32:
+        x = torch.from_numpy(np.ascontiguousarray(psi.astype(np.complex64))).cuda()
+        out = torch.zeros_like(x)
+        W.apply_D(g, 0.05, x, out, N, p)
+        got = out.cpu().numpy().astype(np.complex128)
+    else:
+        # FP16 batches: half2 [V,12,N] then float scale [V,N]; build on host
+        sc = np.max(np.maximum(np.abs(psi.real), np.abs(psi.imag)), axis=1)  # [V,N]
+        h = np.empty((V, 12, N, 2), dtype=np.float16)
+        h[..., 0] = (psi.real / sc[:, None, :]).astype(np.float16)
+        h[..., 1] = (psi.imag / sc[:, None, :]).astype(np.float16)
+        buf = np.concatenate([h.view(np.uint8).ravel(), sc.astype(np.float32).view(np.uint8).ravel()])
+        x = torch.from_numpy(buf).cuda()
+        out = torch.zeros_like(x)
+        W.apply_D(g, 0.05, x, out, N, p)
+        ob = out.cpu().numpy()
+        nh = V * 12 * N * 4
+        hh = ob[:nh].view(np.float16).reshape(V, 12, N, 2).astype(np.float64)
+        s2 = ob[nh:].view(np.float32).reshape(V, N).astype(np.float64)
+        got = (hh[..., 0] + 1j * hh[..., 1]) * s2[:, None, :]
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    assert err < tol, err
+
+
+def test_apply_D_full_size_sampled():
+    """16^3x32 with 48 RHS (the probing workload's shape): sampled sites
+    against the oracle's row-by-row definition, plus gamma5-hermiticity."""
+    dims, N = (16, 16, 16, 32), 48
+    say("apply_D full size", dims, N)
+    V = int(np.prod(dims))
+    U = gauge_field(dims, 0.5, seed=2)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    rng = np.random.default_rng(5)
+    x = torch.randn((V, 12, N), dtype=torch.complex128, device="cuda")
+    out = lat.new_batch(N)
+    W.apply_D(g, 0.02, x, out, N, W.FP64)
+    torch.cuda.synchronize()
+    xs = x.cpu().numpy()
+    sites = list(rng.integers(0, V, 24)) + [0, V - 1, 16 * 16 * 16 * 31, 15, 4095]
+    ref = dirac.apply_D_sites(U, 0.02, xs, dims, sites, -1)
+    got = out.cpu().numpy()[sites]
+    assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(ref))
+    # <y, D x> = <D^dag y, x> at full size
+    y = torch.randn((V, 12, 4), dtype=torch.complex128, device="cuda")
+    xx = x[:, :, :4].contiguous()
+    Dx = lat.new_batch(4)
+    Ddy = lat.new_batch(4)
+    W.apply_D(g, 0.02, xx, Dx, 4, W.FP64)
+    W.apply_D(g, 0.02, y, Ddy, 4, W.FP64, dagger=True)
+    a = torch.sum(torch.conj(y) * Dx, dim=(0, 1))
+    b = torch.sum(torch.conj(Ddy) * xx, dim=(0, 1))
+    assert torch.max(torch.abs(a - b) / torch.abs(a)).item() < 1e-12
+
+
+def test_pack_unpack_roundtrip():
+    dims, N = (4, 2, 4, 6), 7
+    say("pack/unpack", dims, N)
+    lat = W.Lattice(dims, -1)
+    V = lat.V
+    rng = np.random.default_rng(9)
+    nat = rng.standard_normal((N, V, 12)) + 1j * rng.standard_normal((N, V, 12))
+    nat_t = torch.from_numpy(nat).cuda()
+    batch = lat.new_batch(N)
+    W.pack(lat, nat_t, batch, N)
+    assert np.array_equal(batch.cpu().numpy(), np.transpose(nat, (1, 2, 0)))
+    back = torch.zeros_like(nat_t)
+    W.unpack(lat, batch, back, N)
+    assert np.array_equal(back.cpu().numpy(), nat)
+
+
+# ---------------------------------------------------------------------------
+# solve + contraction: the 4^4 Hutchinson workload against dense LU
+
+@pytest.fixture(scope="module")
+def c1():
+    dims, m0 = (4, 4, 4, 4), 0.2
+    U = gauge_field(dims, 0.3, seed=1)
+    D = dirac.dense_D(U, m0, dims, -1)
+    Dinv = osolve.dense_inverse(D)
+    return dims, m0, U, Dinv
+
+
+def _hutchinson_gpu(c1, prec, tol, N=32):
+    dims, m0, U, Dinv = c1
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    b = lat.new_batch(N)
+    W.sources(lat, W.source_descs(list(range(N))), b)
+    x = lat.new_batch(N)
+    rc, st = W.solve(g, m0, b, x, N, tol=tol, prec=prec)
+    full = W.contract(lat, b, x, N)                      # [N, Lt]
+    loop0 = W.contract(lat, b, x, N, spin=gamma.GAMMA5)[:, 0]
+    return lat, b, x, st, full.sum(axis=1), loop0
+
+
+def _oracle_samples(c1, N=32):
+    dims, m0, U, Dinv = c1
+    V = int(np.prod(dims))
+    E = np.stack([noise.rademacher(s, 12 * V) for s in range(N)], axis=1).astype(complex)
+    X = Dinv @ E
+    s_full = np.einsum("ik,ik->k", np.conj(E), X)
+    s_loop = np.array([estimator.sample_dot(E[:, k], X[:, k], dims, t=0, spin=gamma.GAMMA5)
+                       for k in range(N)])
+    return E, X, s_full, s_loop
+
+
+def test_hutchinson_fp64_matches_dense_lu(c1):
+    say("hutchinson 4^4 fp64")
+    lat, b, x, st, s_full, s_loop = _hutchinson_gpu(c1, W.FP64, 1e-12)
+    E, X, o_full, o_loop = _oracle_samples(c1)
+    assert all(s["converged"] for s in st)
+    assert max(s["true_residual"] for s in st) <= 1e-12
+    xs = x.cpu().numpy().reshape(-1, 32)
+    assert np.max(np.linalg.norm(xs - X, axis=0) / np.linalg.norm(X, axis=0)) < 1e-10
+    norms = np.linalg.norm(E, axis=0) * np.linalg.norm(X, axis=0)
+    assert np.all(np.abs(s_full - o_full) <= 1e-10 * norms)
+    assert np.all(np.abs(s_loop - o_loop) <= 1e-10 * norms)
+    T_gpu, T_orc = s_full.mean(), o_full.mean()
+    assert abs(T_gpu - T_orc) <= 1e-10 * max(abs(T_orc), np.mean(np.abs(o_full)))
+    L_gpu, L_orc = s_loop.mean(), o_loop.mean()
+    assert abs(L_gpu - L_orc) <= 1e-10 * max(abs(L_orc), np.mean(np.abs(o_loop)))
+
+
+@pytest.mark.parametrize("prec", ["fp16", "fp32"])
+def test_hutchinson_mixed_matches_dense_lu(c1, prec):
+    say("hutchinson 4^4 mixed", prec)
+    p = W.FP16 if prec == "fp16" else W.FP32
+    lat, b, x, st, s_full, s_loop = _hutchinson_gpu(c1, p, 1e-10)
+    E, X, o_full, o_loop = _oracle_samples(c1)
+    assert all(s["converged"] for s in st), st
+    assert max(s["true_residual"] for s in st) <= 1e-10
+    assert min(s["outer"] for s in st) >= 2
+    norms = np.linalg.norm(E, axis=0) * np.linalg.norm(X, axis=0)
+    assert np.all(np.abs(s_full - o_full) <= 1e-8 * norms)
+    assert np.all(np.abs(s_loop - o_loop) <= 1e-8 * norms)
+    T_gpu, T_orc = s_full.mean(), o_full.mean()
+    assert abs(T_gpu - T_orc) <= 1e-8 * max(abs(T_orc), np.mean(np.abs(o_full)))
+
+
+def test_solve_bit_reproducible(c1):
+    say("solve reproducibility")
+    _, _, x1, _, _, _ = _hutchinson_gpu(c1, W.FP64, 1e-12, N=8)
+    _, _, x2, _, _, _ = _hutchinson_gpu(c1, W.FP64, 1e-12, N=8)
+    assert torch.equal(x1, x2)
+
+
+def test_full_probing_dilution_exact_trace():
+    """Full colouring x 12 dilution on 2^3x4: the estimate equals tr D^-1 and
+    O(t) exactly (up to the solver tolerance)."""
+    dims, m0 = (2, 2, 2, 4), 0.1
+    say("full probing exactness", dims)
+    V = int(np.prod(dims))
+    U = gauge_field(dims, 0.4, seed=2)
+    Dinv = osolve.dense_inverse(dirac.dense_D(U, m0, dims, -1))
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    sig = (1, 2, 4, 8)
+    N = V * 12
+    descs = W.source_descs([3] * N, n_c=V, colour=[j for j in range(V) for _ in range(12)],
+                           sigma=sig, component=[k for _ in range(V) for k in range(12)])
+    b = lat.new_batch(N)
+    W.sources(lat, descs, b)
+    x = lat.new_batch(N)
+    W.solve(g, m0, b, x, N, tol=1e-12, prec=W.FP64)
+    tr = W.contract(lat, b, x, N).sum()
+    assert abs(tr - np.trace(Dinv)) < 1e-10 * abs(np.trace(Dinv))
+    for t in range(dims[3]):
+        o = W.contract(lat, b, x, N, spin=gamma.GAMMA5)[:, t].sum()
+        assert abs(o - estimator.exact_loop(Dinv, dims, t)) < 1e-10 * abs(np.trace(Dinv)) / V
+
+
+def test_correlator_norm2_per_t():
+    dims, m0, N = (4, 4, 2, 6), 0.3, 6
+    say("norm2 per t", dims)
+    V = int(np.prod(dims))
+    lat = W.Lattice(dims, -1)
+    x = rand_batch(V, N, 3)
+    got = W.contract(lat, None, to_dev(x), N, mode=W.CONTRACT_NORM2)
+    for k in range(N):
+        ref = estimator.sample_norm2_per_t(x[:, :, k], dims)
+        assert np.allclose(got[k], ref, rtol=1e-14, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# backward force
+
+def test_force_matches_oracle():
+    dims, m0, N = (4, 4, 2, 4), 0.2, 4
+    say("force", dims, N)
+    V = int(np.prod(dims))
+    U = gauge_field(dims, 0.4, seed=6)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    xs = rand_batch(V, N, 11)
+    ys = rand_batch(V, N, 12)
+    gout = np.array([1.0, 1j, 0.3 - 0.7j, -2.0 + 0.5j])
+    gU = torch.zeros((V, 4, 3, 3), dtype=torch.complex128, device="cuda")
+    gm = W.force(g, to_dev(xs), to_dev(ys), N, gout, gU)
+    refU = oforce.grad_links([xs[:, :, k] for k in range(N)], [ys[:, :, k] for k in range(N)],
+                             gout, dims, -1)
+    refm = oforce.grad_m0([xs[:, :, k] for k in range(N)], [ys[:, :, k] for k in range(N)], gout)
+    assert np.max(np.abs(gU.cpu().numpy() - refU)) < 1e-13 * np.max(np.abs(refU))
+    assert abs(gm - refm) < 1e-12 * abs(refm)

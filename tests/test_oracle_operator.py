@@ -145,3 +145,16 @@ def test_exact_traces_real_by_gamma5_hermiticity():
     for t in range(4):
         o = estimator.exact_loop(Dinv, dims, t)
         assert abs(o.imag) < 1e-11
+
+
+@pytest.mark.parametrize("dagger", [False, True])
+def test_sampled_rows_match_sparse(dagger):
+    dims = (4, 2, 2, 6)
+    V = geometry.volume(dims)
+    U = gauge_field(dims, 0.6, seed=12)
+    rng = np.random.default_rng(1)
+    psi = rng.standard_normal((V, 12, 2)) + 1j * rng.standard_normal((V, 12, 2))
+    full = dirac.apply_D(U, 0.3, psi, dims, -1, dagger=dagger)
+    sites = [0, 3, 17, 40, V - 1, 8, 88]
+    part = dirac.apply_D_sites(U, 0.3, psi, dims, sites, -1, dagger=dagger)
+    assert np.max(np.abs(part - full[sites])) < 1e-14
