@@ -235,6 +235,17 @@ typedef struct {
     double bytes;
 } wdt_prof_entry;
 
+/*
+ * Launch-shape overrides for the tuner (all kernels over (site, rhs)):
+ * rhs_tile = right-hand sides per tile (the batch is swept tile by tile),
+ * sites_per_block = sites a block handles per step, max_blocks = blocks per
+ * tile, z_slab = thickness (a divisor of Lz) of the z-slabs of the order in
+ * which sites are visited (t-neighbours are Lx*Ly*z_slab sites apart in that
+ * order).  0 restores the automatic choice.  Process-wide; not thread-safe.
+ */
+int wdt_set_launch_shape(int32_t rhs_tile, int32_t sites_per_block, int32_t max_blocks,
+                         int32_t z_slab);
+
 int wdt_profile_enable(int on);
 /* Fills up to max entries; *n receives the number of kernel classes. */
 int wdt_profile_read(wdt_prof_entry *out, int32_t max, int32_t *n);

@@ -34,7 +34,7 @@ size_t site_bytes(int prec) {
     return prec == WDT_FP64 ? 192 : prec == WDT_FP32 ? 96 : 52;
 }
 size_t link_bytes(int prec) {
-    return prec == WDT_FP64 ? 144 : prec == WDT_FP32 ? 72 : 36;
+    return prec == WDT_FP64 ? 144 : 72;  // FP16 storage uses FP32 links
 }
 
 // ---------------------------------------------------------------------------
@@ -103,14 +103,12 @@ ProfScope::~ProfScope() {
     if (stop) (void)hipEventRecord(stop, stream);
 }
 
-// Converts FP64 links to the FP32 and FP16 copies.
-__global__ void k_links_lower(const double2 *__restrict__ U, float2 *__restrict__ U32,
-                              __half2 *__restrict__ U16, int64_t n) {
+// Converts FP64 links to the FP32 copy (used by the FP32 and FP16 operators).
+__global__ void k_links_lower(const double2 *__restrict__ U, float2 *__restrict__ U32, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double2 u = U[i];
         U32[i] = make_float2((float)u.x, (float)u.y);
-        U16[i] = __floats2half2_rn((float)u.x, (float)u.y);
     }
 }
 
@@ -228,25 +226,22 @@ int wdt_gauge_create(wdt_lattice lat, const double *host_links, wdt_gauge *out) 
     const int64_t n = lat->V * 4 * 9;
     hipError_t e1 = hipMalloc(&g->U64, n * sizeof(double2));
     hipError_t e2 = hipMalloc(&g->U32, n * sizeof(float2));
-    hipError_t e3 = hipMalloc(&g->U16, n * sizeof(__half2));
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+    if (e1 != hipSuccess || e2 != hipSuccess) {
         (void)hipGetLastError();
         if (g->U64) (void)hipFree(g->U64);
         if (g->U32) (void)hipFree(g->U32);
-        if (g->U16) (void)hipFree(g->U16);
         delete g;
         return set_error(WDT_ENOMEM, "wdt_gauge_create: device allocation failed");
     }
     hipError_t e = hipMemcpy(g->U64, host_links, n * sizeof(double2), hipMemcpyHostToDevice);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_links_lower, dim3(1024), dim3(256), 0, 0, g->U64, g->U32, g->U16, n);
+        hipLaunchKernelGGL(k_links_lower, dim3(1024), dim3(256), 0, 0, g->U64, g->U32, n);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         (void)hipFree(g->U64);
         (void)hipFree(g->U32);
-        (void)hipFree(g->U16);
         delete g;
         return set_error(WDT_EHIP, "wdt_gauge_create: %s", hipGetErrorString(e));
     }
@@ -258,7 +253,6 @@ int wdt_gauge_destroy(wdt_gauge g) {
     if (!g) return WDT_OK;
     (void)hipFree(g->U64);
     (void)hipFree(g->U32);
-    (void)hipFree(g->U16);
     if (g->ws.ptr) (void)hipFree(g->ws.ptr);
     delete g;
     return WDT_OK;
@@ -267,6 +261,20 @@ int wdt_gauge_destroy(wdt_gauge g) {
 int wdt_gauge_get(wdt_gauge g, double *host_links) {
     WDT_CHECK(g && host_links, "wdt_gauge_get: null argument");
     WDT_HIP(hipMemcpy(host_links, g->U64, g->lat.V * 36 * sizeof(double2), hipMemcpyDeviceToHost));
+    return WDT_OK;
+}
+
+int wdt_set_launch_shape(int32_t rhs_tile, int32_t sites_per_block, int32_t max_blocks,
+                         int32_t z_slab) {
+    WDT_CHECK(rhs_tile >= 0 && rhs_tile <= 256, "wdt_set_launch_shape: rhs_tile must be 0..256");
+    WDT_CHECK(sites_per_block >= 0 && sites_per_block <= 256,
+              "wdt_set_launch_shape: sites_per_block must be 0..256");
+    WDT_CHECK(max_blocks >= 0, "wdt_set_launch_shape: max_blocks must be >= 0");
+    tuning().nt = rhs_tile;
+    tuning().sb = sites_per_block;
+    WDT_CHECK(z_slab >= 0, "wdt_set_launch_shape: z_slab must be >= 0");
+    tuning().gmax = max_blocks;
+    tuning().bz = z_slab;
     return WDT_OK;
 }
 

@@ -45,7 +45,46 @@ struct Geom {
     int V;
     int Lxyz;
     int bc_t;
+    // Processing order of the sites (see site_of): tiles of Lx*Ly*bz*bt sites.
+    int bz, bt;
 };
+
+// Site index of processing position p.  The lattice is cut into tiles of
+// Lx*Ly*bz*bt sites, z-tiles fastest, then t-tiles; inside a tile x runs
+// fastest, then y, z, t.  Consecutive positions are then close in all four
+// directions (a t-neighbour is Lx*Ly*bz positions away instead of Lx*Ly*Lz),
+// which lets an XCD's L2 serve the neighbour re-reads of the operator.
+__device__ __forceinline__ int site_of(const Geom &g, int p) {
+    if (g.bz == g.L[2] && g.bt == g.L[3]) return p;
+    const int tvol = g.Lxyz / g.L[2] * g.bz * g.bt;
+    const int tile = p / tvol;
+    int q = p - tile * tvol;
+    const int nzt = g.L[2] / g.bz;
+    const int zt = tile % nzt, tt = tile / nzt;
+    const int xy = q % (g.L[0] * g.L[1]);
+    q /= g.L[0] * g.L[1];
+    const int z = zt * g.bz + q % g.bz;
+    const int t = tt * g.bt + q / g.bz;
+    return xy + g.L[0] * g.L[1] * (z + g.L[2] * t);
+}
+
+// Work split of a (site, rhs) kernel: with a grid of G blocks (G a multiple
+// of 8), the blocks on XCD k sweep the k-th eighth of the processing order
+// in steps of G/8 groups, so each XCD streams through one contiguous region.
+struct Sweep {
+    int first, end, step;
+};
+__device__ __forceinline__ Sweep sweep(int ngroups, int Lb, int G) {
+    const int nx = (G % 8 == 0) ? 8 : 1;
+    const int Gx = G / nx;
+    const int xcd = Lb / Gx, j = Lb - xcd * Gx;
+    const int gpx = (ngroups + nx - 1) / nx;
+    Sweep w;
+    w.first = xcd * gpx + j;
+    w.end = min(ngroups, (xcd + 1) * gpx);
+    w.step = Gx;
+    return w;
+}
 
 struct SiteNbr {
     int fwd[4], bwd[4];
@@ -75,19 +114,25 @@ __device__ __forceinline__ SiteNbr neighbours(const Geom &g, int s) {
 // Spinor batch formats: [V][12][N] with the RHS index innermost.
 //  F64: double2; F32: float2; F16: __half2 plus a float scale per (site, rhs)
 //  stored after the V*12*N half2 values.
+//  `link` is the element type of the links the operator reads: FP16 storage
+//  keeps FP32 links (they are a small share of the bytes, and converting a
+//  link in every lane would cost more ALU time than it saves in traffic).
 struct F64 {
     using real = double;
     using elem = double2;
+    using link = double2;
     static constexpr bool scaled = false;
 };
 struct F32 {
     using real = float;
     using elem = float2;
+    using link = float2;
     static constexpr bool scaled = false;
 };
 struct F16 {
     using real = float;
     using elem = __half2;
+    using link = float2;
     static constexpr bool scaled = true;
 };
 
@@ -105,67 +150,99 @@ template <class S> __host__ __device__ inline SpinorPtr<S> make_spinor(void *bas
     return s;
 }
 
-template <class S>
-__device__ __forceinline__ void load_site(const SpinorPtr<S> &sp, int site, int r,
-                                          cplx<typename S::real> (&v)[12]) {
-    const size_t base = (size_t)site * 12 * sp.N + r;
+// NC > 0: the batch size is the compile-time constant NC, so the 12 component
+// offsets of a site become immediate offsets of one address.
+template <class S, int NC = 0>
+__device__ __forceinline__ int batch_n(const SpinorPtr<S> &sp) {
+    return NC > 0 ? NC : sp.N;
+}
+
+// The 12 components of (site, r) without the FP16 scale applied; returns the
+// scale (1 for unscaled formats).
+template <class S, int NC = 0>
+__device__ __forceinline__ typename S::real load_site_raw(const SpinorPtr<S> &sp, int site, int r,
+                                                          cplx<typename S::real> (&v)[12]) {
+    const int N = batch_n<S, NC>(sp);
+    const typename S::elem *q = sp.p + (size_t)site * 12 * N + r;
     if constexpr (S::scaled) {
-        const float sc = sp.scale[(size_t)site * sp.N + r];
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            float2 f = __half22float2(sp.p[base + (size_t)k * sp.N]);
-            v[k] = {f.x * sc, f.y * sc};
+            const float2 f = __half22float2(q[k * N]);
+            v[k] = {f.x, f.y};
         }
+        return sp.scale[(size_t)site * N + r];
     } else {
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            auto e = sp.p[base + (size_t)k * sp.N];
+            const auto e = q[k * N];
             v[k] = {e.x, e.y};
         }
+        return typename S::real(1);
     }
 }
 
-template <class S>
+template <class S, int NC = 0>
+__device__ __forceinline__ void load_site(const SpinorPtr<S> &sp, int site, int r,
+                                          cplx<typename S::real> (&v)[12]) {
+    const typename S::real sc = load_site_raw<S, NC>(sp, site, r, v);
+    if constexpr (S::scaled) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = {v[k].re * sc, v[k].im * sc};
+    }
+}
+
+// STREAM = true marks the stores non-temporal, so a kernel's output does not
+// displace the input lines its neighbours still have to re-read from L2.
+template <class S, bool STREAM = false, int NC = 0>
 __device__ __forceinline__ void store_site(const SpinorPtr<S> &sp, int site, int r,
                                            const cplx<typename S::real> (&v)[12]) {
-    const size_t base = (size_t)site * 12 * sp.N + r;
+    const int N = batch_n<S, NC>(sp);
+    const size_t base = (size_t)site * 12 * N + r;
     if constexpr (S::scaled) {
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
         const float inv = (m > 0.f) ? 1.0f / m : 0.f;
 #pragma unroll
-        for (int k = 0; k < 12; ++k)
-            sp.p[base + (size_t)k * sp.N] = __floats2half2_rn(v[k].re * inv, v[k].im * inv);
-        sp.scale[(size_t)site * sp.N + r] = m;
+        for (int k = 0; k < 12; ++k) {
+            const __half2 h = __floats2half2_rn(v[k].re * inv, v[k].im * inv);
+            if constexpr (STREAM) {
+                unsigned u;
+                __builtin_memcpy(&u, &h, 4);
+                __builtin_nontemporal_store(u, reinterpret_cast<unsigned *>(sp.p + base + k * N));
+            } else {
+                sp.p[base + k * N] = h;
+            }
+        }
+        if constexpr (STREAM)
+            __builtin_nontemporal_store(m, sp.scale + (size_t)site * N + r);
+        else
+            sp.scale[(size_t)site * N + r] = m;
     } else {
         using E = typename S::elem;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            E e;
-            e.x = v[k].re;
-            e.y = v[k].im;
-            sp.p[base + (size_t)k * sp.N] = e;
+            E *q = sp.p + base + k * N;
+            if constexpr (STREAM) {
+                __builtin_nontemporal_store(v[k].re, &q->x);
+                __builtin_nontemporal_store(v[k].im, &q->y);
+            } else {
+                E e;
+                e.x = v[k].re;
+                e.y = v[k].im;
+                *q = e;
+            }
         }
     }
 }
 
-// Gauge links [V][4][9] in the element type of the precision.
-template <class S> struct LinkElem { using type = typename S::elem; };
-
+// Gauge links [V][4][9] in the link type of the precision.
 template <class S, class R>
-__device__ __forceinline__ void load_link(const typename S::elem *U, int site, int mu,
+__device__ __forceinline__ void load_link(const typename S::link *U, int site, int mu,
                                           cplx<R> (&u)[9]) {
-    const typename S::elem *q = U + ((size_t)site * 4 + mu) * 9;
+    const typename S::link *q = U + ((size_t)site * 4 + mu) * 9;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        if constexpr (S::scaled) {
-            float2 f = __half22float2(q[k]);
-            u[k] = {f.x, f.y};
-        } else {
-            u[k] = {(R)q[k].x, (R)q[k].y};
-        }
-    }
+    for (int k = 0; k < 9; ++k) u[k] = {(R)q[k].x, (R)q[k].y};
 }
 
 // ---------------------------------------------------------------------------
@@ -242,22 +319,22 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }
 
 // Loop of a (site, rhs) kernel: thread (rl, ry) of a block of NT*SB threads
-// handles RHS blockIdx.y*NT + rl and site ry of each group of SB sites in the
-// block's chunk.  Expects V, N, NT, SB, chunk in scope.
-#define SITE_LOOP_BEGIN                                              \
-    const int tid = threadIdx.x;                                     \
-    const int rl = tid % NT;                                         \
-    const int ry = tid / NT;                                         \
-    const int r = blockIdx.y * NT + rl;                              \
-    const bool live = (ry < SB) && (r < N);                          \
-    const int Lb = xcd_block(blockIdx.x, gridDim.x);                 \
-    const int ngroups = (V + SB - 1) / SB;                           \
-    const int g0 = Lb * chunk;                                       \
-    const int g1 = min(ngroups, g0 + chunk);                         \
-    if (live)                                                        \
-        for (int grp = g0; grp < g1; ++grp) {                        \
-            const int s = grp * SB + ry;                             \
-            if (s >= V) break;
+// handles RHS blockIdx.y*NT + rl and position ry of each group of SB
+// consecutive processing positions the block's sweep visits.  Expects a Geom
+// g and N, NT, SB in scope.
+#define SITE_LOOP_BEGIN                                                    \
+    const int tid = threadIdx.x;                                           \
+    const int rl = tid % NT;                                               \
+    const int ry = tid / NT;                                               \
+    const int r = blockIdx.y * NT + rl;                                    \
+    const bool live = (ry < SB) && (r < N);                                \
+    const int Lb = xcd_block(blockIdx.x, gridDim.x);                       \
+    const Sweep sw_ = sweep((g.V + SB - 1) / SB, Lb, gridDim.x);           \
+    if (live)                                                              \
+        for (int grp = sw_.first; grp < sw_.end; grp += sw_.step) {        \
+            const int p_ = grp * SB + ry;                                  \
+            if (p_ >= g.V) break;                                          \
+            const int s = site_of(g, p_);
 
 #define SITE_LOOP_END }
 

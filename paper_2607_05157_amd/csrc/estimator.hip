@@ -22,10 +22,8 @@ __device__ __forceinline__ uint64_t splitmix_word(uint64_t c) {
 
 template <class S>
 __global__ __launch_bounds__(256) void k_sources(Geom g, const wdt_source_desc *__restrict__ desc,
-                                                 int N, int NT, int SB, int chunk,
-                                                 SpinorPtr<S> out) {
+                                                 int N, int NT, int SB, SpinorPtr<S> out) {
     using R = typename S::real;
-    const int V = g.V;
     SITE_LOOP_BEGIN
     const wdt_source_desc d = desc[r];
     int c[4];
@@ -201,9 +199,12 @@ static int contract(const wdt_lattice_s *lat, const void *src, const void *sol, 
                     const double *B, int mode, double2 *host_out, hipStream_t stream) {
     const Geom g = lat->geom();
     const int Lt = g.L[3];
-    const int NT = N < 256 ? N : 256;
-    const Shape sh = site_shape(g.Lxyz, N);
-    const int nb = sh.G;
+    const Shape sh = site_shape(*lat, N, WDT_FP64);
+    const int NT = sh.NT;
+    // blocks per slice and site groups per block for the slice-wise sums
+    const int ngs = (g.Lxyz + sh.SB - 1) / sh.SB;
+    const int nb = std::max(1, std::min(ngs, 2048 / std::max(1, Lt)));
+    const int chunk = (ngs + nb - 1) / nb;
     SpinMat Bm;
     for (int i = 0; i < 16; ++i)
         Bm.m[i] = B ? make_double2(B[2 * i], B[2 * i + 1])
@@ -215,15 +216,15 @@ static int contract(const wdt_lattice_s *lat, const void *src, const void *sol, 
         (void)hipGetLastError();
         return set_error(WDT_ENOMEM, "contract: scratch allocation failed");
     }
-    const dim3 grid(nb, Lt, (N + NT - 1) / NT);
+    const dim3 grid(nb, Lt, sh.tiles);
     SpinorPtr<F64> ps = make_spinor<F64>(const_cast<void *>(src), g.V, N);
     SpinorPtr<F64> px = make_spinor<F64>(const_cast<void *>(sol), g.V, N);
     if (mode == WDT_CONTRACT_DOT)
         hipLaunchKernelGGL(k_contract<0>, grid, dim3(sh.threads), 0, stream, g, ps, px, N, NT,
-                           sh.SB, sh.chunk, Bm, buf);
+                           sh.SB, chunk, Bm, buf);
     else
         hipLaunchKernelGGL(k_contract<1>, grid, dim3(sh.threads), 0, stream, g, ps, px, N, NT,
-                           sh.SB, sh.chunk, Bm, buf);
+                           sh.SB, chunk, Bm, buf);
     double2 *outd = (double2 *)((char *)buf + pbytes);
     hipLaunchKernelGGL(k_contract_reduce, dim3((N * Lt + 255) / 256), dim3(256), 0, stream, buf,
                        nb, N, Lt, outd);
@@ -386,22 +387,22 @@ int wdt_sources(wdt_lattice lat, const wdt_source_desc *desc, int32_t n_rhs, voi
         return set_error(WDT_ENOMEM, "wdt_sources: scratch allocation failed");
     }
     WDT_HIP(hipMemcpyAsync(dd, desc, sizeof(wdt_source_desc) * n_rhs, hipMemcpyHostToDevice, st));
-    const Geom g = lat->geom();
-    const Shape sh = site_shape(g.V, n_rhs);
-    const int NT = n_rhs < 256 ? n_rhs : 256;
-    const dim3 grid(sh.G, (n_rhs + NT - 1) / NT);
+    const Shape sh = site_shape(*lat, n_rhs, prec);
+    const Geom g = shaped_geom(*lat, sh);
+    const int NT = sh.NT;
+    const dim3 grid(sh.G, sh.tiles);
     switch (prec) {
         case WDT_FP64:
             hipLaunchKernelGGL(k_sources<F64>, grid, dim3(sh.threads), 0, st, g, dd, n_rhs, NT,
-                               sh.SB, sh.chunk, make_spinor<F64>(dev_out, g.V, n_rhs));
+                               sh.SB, make_spinor<F64>(dev_out, g.V, n_rhs));
             break;
         case WDT_FP32:
             hipLaunchKernelGGL(k_sources<F32>, grid, dim3(sh.threads), 0, st, g, dd, n_rhs, NT,
-                               sh.SB, sh.chunk, make_spinor<F32>(dev_out, g.V, n_rhs));
+                               sh.SB, make_spinor<F32>(dev_out, g.V, n_rhs));
             break;
         default:
             hipLaunchKernelGGL(k_sources<F16>, grid, dim3(sh.threads), 0, st, g, dd, n_rhs, NT,
-                               sh.SB, sh.chunk, make_spinor<F16>(dev_out, g.V, n_rhs));
+                               sh.SB, make_spinor<F16>(dev_out, g.V, n_rhs));
             break;
     }
     WDT_HIP(hipGetLastError());

@@ -26,6 +26,8 @@ struct wdt_lattice_s {
         g.V = (int)V;
         g.Lxyz = g.stride[3];
         g.bc_t = bc_t;
+        g.bz = dims[2];
+        g.bt = dims[3];
         return g;
     }
 };
@@ -41,7 +43,6 @@ struct wdt_gauge_s {
     wdt_lattice_s lat;
     double2 *U64 = nullptr;
     float2 *U32 = nullptr;
-    __half2 *U16 = nullptr;
     Workspace ws;
 };
 
@@ -83,15 +84,31 @@ struct ProfScope {
     hipStream_t stream;
 };
 
-// Launch shape of the (site, rhs) kernels: blocks of N*SB threads handle SB
-// sites at a time; G blocks (a multiple of 8 when large) sweep the lattice.
+// Launch shape of the (site, rhs) kernels: the RHS batch is cut into tiles
+// of NT right-hand sides (grid.y); blocks of NT*SB threads handle SB sites of
+// one tile at a time, and G blocks (a multiple of 8 when large) sweep the
+// lattice for each tile.  Tiles keep the per-site working set small enough
+// for the caches to serve the neighbour re-reads of the operator.
 struct Shape {
+    int NT;       // right-hand sides per tile
+    int tiles;    // ceil(N / NT)
     int SB;       // sites per block iteration
-    int threads;  // block size (N*SB rounded up to a multiple of 64)
-    int G;        // grid size
-    int chunk;    // site groups per block
+    int threads;  // block size (NT*SB rounded up to a multiple of 64)
+    int G;        // operator blocks per tile (about the number the GPU holds at once)
+    int Gv;       // blocks per tile of the vector (BLAS-1) kernels
+    int bz, bt;   // processing-order tile (see site_of)
 };
-Shape site_shape(int64_t V, int N);
+Shape site_shape(const wdt_lattice_s &lat, int N, int prec);
+// Resident blocks per CU of the operator kernel for (prec, N, block size).
+int op_blocks_per_cu(int prec, int N, int threads);
+// The lattice geometry with the processing order of a shape.
+wdt::Geom shaped_geom(const wdt_lattice_s &lat, const Shape &sh);
+
+// Launch-shape overrides for the tuner (0 = automatic).
+struct LaunchTuning {
+    int nt = 0, sb = 0, gmax = 0, bz = 0;
+};
+LaunchTuning &tuning();
 
 // Epilogues of the operator kernel.
 enum Epi { EPI_NONE = 0, EPI_DOT_AUX = 1, EPI_DOT_TS = 2, EPI_RESID = 3 };

@@ -162,7 +162,7 @@ __device__ __forceinline__ cplx<Rl<S>> to_c(double2 a) {
 
 // s = r - alpha v
 template <class S>
-__global__ __launch_bounds__(256) void k_update_s(int V, int N, int NT, int SB, int chunk,
+__global__ __launch_bounds__(256) void k_update_s(Geom g, int N, int NT, int SB,
                                                   const RhsState *__restrict__ st, SpinorPtr<S> rv,
                                                   SpinorPtr<S> vv, SpinorPtr<S> sv) {
     using R = Rl<S>;
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_update_s(int V, int N, int NT, int SB, 
 
 // x += alpha p + omega s;  r = s - omega t;  partials: rhat^dag r, ||r||^2
 template <class S>
-__global__ __launch_bounds__(256) void k_update_xr(int V, int N, int NT, int SB, int chunk,
+__global__ __launch_bounds__(256) void k_update_xr(Geom g, int N, int NT, int SB,
                                                    const RhsState *__restrict__ st, SpinorPtr<S> xv,
                                                    SpinorPtr<S> pv, SpinorPtr<S> sv,
                                                    SpinorPtr<S> tv, SpinorPtr<S> rv,
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void k_update_xr(int V, int N, int NT, int SB,
 
 // p = r + beta (p - omega v)
 template <class S>
-__global__ __launch_bounds__(256) void k_update_p(int V, int N, int NT, int SB, int chunk,
+__global__ __launch_bounds__(256) void k_update_p(Geom g, int N, int NT, int SB,
                                                   const RhsState *__restrict__ st, SpinorPtr<S> rv,
                                                   SpinorPtr<S> pv, SpinorPtr<S> vv) {
     using R = Rl<S>;
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(256) void k_update_p(int V, int N, int NT, int SB, 
 
 // dst(T) = src(S) converted (and optionally dst += src when ADD)
 template <class SS, class SD, bool ADD>
-__global__ __launch_bounds__(256) void k_convert(int V, int N, int NT, int SB, int chunk,
+__global__ __launch_bounds__(256) void k_convert(Geom g, int N, int NT, int SB,
                                                  SpinorPtr<SS> src, SpinorPtr<SD> dst) {
     SITE_LOOP_BEGIN
     cplx<Rl<SS>> a[12];
@@ -267,27 +267,96 @@ __global__ __launch_bounds__(256) void k_convert(int V, int N, int NT, int SB, i
 // ---------------------------------------------------------------------------
 // Host side.
 
-Shape site_shape(int64_t V, int N) {
+LaunchTuning &tuning() {
+    static LaunchTuning t;
+    return t;
+}
+
+// Default RHS tile: the largest divisor of N not above a per-precision target
+// (narrower tiles for wider storage keep the per-site footprint small), or
+// the target itself.
+static int default_nt(int N, int prec) {
+    const int target = prec == WDT_FP64 ? 8 : prec == WDT_FP32 ? 16 : 48;
+    if (N <= target) return N;
+    for (int d = target; d >= 8; --d)
+        if (N % d == 0) return d;
+    return target;
+}
+
+static int device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        hipDeviceProp_t p;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+            cus = p.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+Shape site_shape(const wdt_lattice_s &lat, int N, int prec) {
+    const LaunchTuning &tu = tuning();
+    const int64_t V = lat.V;
     Shape sh;
-    const int NT = N < 256 ? N : 256;
+    int NT = tu.nt > 0 ? tu.nt : default_nt(N, prec);
+    NT = std::min(std::min(NT, N), 256);
+    sh.NT = NT;
+    sh.tiles = (N + NT - 1) / NT;
     int SB = std::max(1, 256 / NT);
-    // prefer full wavefronts: largest SB <= 256/NT with NT*SB a multiple of 64
-    for (int sb = SB; sb >= 1; --sb)
-        if ((NT * sb) % 64 == 0) {
-            SB = sb;
-            break;
-        }
+    if (tu.sb > 0) {
+        SB = std::min(tu.sb, SB);
+    } else {
+        // prefer full wavefronts: largest SB <= 256/NT with NT*SB a multiple of 64
+        for (int sb = SB; sb >= 1; --sb)
+            if ((NT * sb) % 64 == 0) {
+                SB = sb;
+                break;
+            }
+    }
     sh.SB = SB;
     sh.threads = ((NT * SB + 63) / 64) * 64;
     const int64_t ngroups = (V + SB - 1) / SB;
-    const int64_t Gmax = 2048;
-    int64_t G = std::min<int64_t>(ngroups, Gmax);
-    int64_t chunk = (ngroups + G - 1) / G;
-    G = (ngroups + chunk - 1) / chunk;
-    if (G >= 8) G = ((G + 7) / 8) * 8;  // XCD-aware renumbering needs a multiple of 8
-    sh.G = (int)G;
-    sh.chunk = (int)chunk;
+    // about as many blocks as the GPU keeps resident (operator kernel occupancy)
+    // FP64 sweeps are limited by L2 capacity (wide sites): one block per CU
+    // keeps the XCD front small; narrower formats fill the CU
+    int per_cu = prec == WDT_FP64 ? 1 : op_blocks_per_cu(prec, N, sh.threads);
+    if (per_cu <= 0) per_cu = 2;
+    const int64_t Gdef = (int64_t)device_cus() * per_cu;
+    int64_t G = std::min<int64_t>(ngroups, tu.gmax > 0 ? tu.gmax : Gdef);
+    // XCD-aware renumbering needs a multiple of 8 (a tuner override is taken
+    // as given, so that the plain round-robin mapping can be measured too)
+    if (G >= 8 && tu.gmax <= 0) G = (G / 8) * 8;
+    sh.G = (int)std::max<int64_t>(G, 1);
+    // streaming vector kernels have no reuse to protect: fill the CUs
+    int64_t Gv = std::min<int64_t>(ngroups, (int64_t)device_cus() * 4);
+    if (Gv >= 8) Gv = (Gv / 8) * 8;
+    sh.Gv = (int)std::max<int64_t>(Gv, 1);
+    // processing-order tile: z-slabs thin enough that two t-strides of the
+    // input tile fit in about 2 MB of L2, whole extent in t
+    const int Lz = lat.dims[2];
+    const double foot = (double)NT * site_bytes(prec);
+    int bz = Lz;
+    if (tu.bz > 0 && Lz % tu.bz == 0) {
+        bz = tu.bz;
+    } else {
+        for (int d = Lz; d >= 1; --d)
+            if (Lz % d == 0) {
+                bz = d;
+                if (2.0 * lat.dims[0] * lat.dims[1] * d * foot <= (prec == WDT_FP64 ? 2.0e6 : 6.0e6))
+                    break;
+            }
+    }
+    sh.bz = bz;
+    sh.bt = lat.dims[3];
     return sh;
+}
+
+Geom shaped_geom(const wdt_lattice_s &lat, const Shape &sh) {
+    Geom g = lat.geom();
+    g.bz = sh.bz;
+    g.bt = sh.bt;
+    return g;
 }
 
 namespace {
@@ -322,6 +391,7 @@ struct Bicg {
     double m0;
     int N, V;
     Shape sh;
+    Geom geo;
     int NT;
     dim3 grid;
     hipStream_t stream;
@@ -350,24 +420,24 @@ int bicgstab_iterate(Bicg &B, int prec, void *x, void *r, void *rhat, void *p, v
         hipLaunchKernelGGL(k_scalar_alpha, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.G, N);
         {
             ProfScope pr(nm_s[prec], 3 * vb, B.stream);
-            hipLaunchKernelGGL((k_update_s<S>), B.grid, dim3(sh.threads), 0, B.stream, V, N, B.NT,
-                               sh.SB, sh.chunk, B.st, sp<S>(r, V, N), sp<S>(v, V, N),
+            hipLaunchKernelGGL((k_update_s<S>), B.grid, dim3(sh.threads), 0, B.stream, B.geo, N, B.NT,
+                               sh.SB, B.st, sp<S>(r, V, N), sp<S>(v, V, N),
                                sp<S>(s, V, N));
         }
         WDT_TRY(launch_dslash(B.g, B.m0, prec, 0, EPI_DOT_TS, s, t, nullptr, N, B.part, sh, B.stream));
         hipLaunchKernelGGL(k_scalar_omega, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.G, N);
         {
             ProfScope pr(nm_xr[prec], 7 * vb, B.stream);
-            hipLaunchKernelGGL((k_update_xr<S>), B.grid, dim3(sh.threads), 0, B.stream, V, N, B.NT,
-                               sh.SB, sh.chunk, B.st, sp<S>(x, V, N), sp<S>(p, V, N),
+            hipLaunchKernelGGL((k_update_xr<S>), B.grid, dim3(sh.threads), 0, B.stream, B.geo, N, B.NT,
+                               sh.SB, B.st, sp<S>(x, V, N), sp<S>(p, V, N),
                                sp<S>(s, V, N), sp<S>(t, V, N), sp<S>(r, V, N), sp<S>(rhat, V, N),
                                B.part);
         }
-        hipLaunchKernelGGL(k_scalar_beta, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.G, N);
+        hipLaunchKernelGGL(k_scalar_beta, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.Gv, N);
         {
             ProfScope pr(nm_p[prec], 4 * vb, B.stream);
-            hipLaunchKernelGGL((k_update_p<S>), B.grid, dim3(sh.threads), 0, B.stream, V, N, B.NT,
-                               sh.SB, sh.chunk, B.st, sp<S>(r, V, N), sp<S>(p, V, N),
+            hipLaunchKernelGGL((k_update_p<S>), B.grid, dim3(sh.threads), 0, B.stream, B.geo, N, B.NT,
+                               sh.SB, B.st, sp<S>(r, V, N), sp<S>(p, V, N),
                                sp<S>(v, V, N));
         }
         WDT_HIP(hipGetLastError());
@@ -391,10 +461,11 @@ int bicgstab_iterate(Bicg &B, int prec, void *x, void *r, void *rhat, void *p, v
 static int solve_fp64(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
                       const wdt_solve_params &P, wdt_rhs_stats *stats, hipStream_t stream) {
     const int V = (int)g->lat.V;
-    const Shape sh = site_shape(V, N);
-    const int NT = N < 256 ? N : 256;
+    const Shape sh = site_shape(g->lat, N, WDT_FP64);
+    const Geom geo = shaped_geom(g->lat, sh);
+    const int NT = sh.NT;
     const size_t vb = spinor_bytes(V, N, WDT_FP64);
-    const size_t part_bytes = (size_t)2 * sh.G * N * sizeof(double2);
+    const size_t part_bytes = (size_t)2 * std::max(sh.G, sh.Gv) * N * sizeof(double2);
     const size_t st_bytes = ((sizeof(RhsState) * N + 255) / 256) * 256;
     const size_t part_off = 6 * vb;
     const size_t st_off = part_off + ((part_bytes + 255) / 256) * 256;
@@ -402,7 +473,7 @@ static int solve_fp64(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
     char *base = (char *)g->ws.ptr;
     void *r = base, *rhat = base + vb, *p = base + 2 * vb, *v = base + 3 * vb, *s = base + 4 * vb,
          *t = base + 5 * vb;
-    Bicg B{g, m0, N, V, sh, NT, dim3(sh.G, (N + NT - 1) / NT), stream,
+    Bicg B{g, m0, N, V, sh, geo, NT, dim3(sh.Gv, sh.tiles), stream,
            (RhsState *)(base + st_off), (double2 *)(base + part_off)};
     WDT_HIP(hipMemsetAsync(B.st, 0, sizeof(RhsState) * N, stream));
     if (!P.x0_is_guess) WDT_HIP(hipMemsetAsync(x, 0, vb, stream));
@@ -453,11 +524,12 @@ template <class S>
 static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N, int prec,
                        const wdt_solve_params &P, wdt_rhs_stats *stats, hipStream_t stream) {
     const int V = (int)g->lat.V;
-    const Shape sh = site_shape(V, N);
-    const int NT = N < 256 ? N : 256;
+    const Shape sh = site_shape(g->lat, N, prec);
+    const Geom geo = shaped_geom(g->lat, sh);
+    const int NT = sh.NT;
     const size_t vb64 = spinor_bytes(V, N, WDT_FP64);
     const size_t vbl = ((spinor_bytes(V, N, prec) + 255) / 256) * 256;
-    const size_t part_bytes = (size_t)2 * sh.G * N * sizeof(double2);
+    const size_t part_bytes = (size_t)2 * std::max(sh.G, sh.Gv) * N * sizeof(double2);
     const size_t st_bytes = ((sizeof(RhsState) * N + 255) / 256) * 256;
     const size_t low_off = vb64;
     const size_t part_off = low_off + 7 * vbl;
@@ -470,9 +542,9 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
     for (int i = 0; i < 7; ++i) lo[i] = base + low_off + i * vbl;
     void *rS = lo[0], *rhat = lo[1], *p = lo[2], *v = lo[3], *s = lo[4], *t = lo[5], *e = lo[6];
     int *mask = (int *)(base + mask_off);
-    Bicg B{g, m0, N, V, sh, NT, dim3(sh.G, (N + NT - 1) / NT), stream,
+    Bicg B{g, m0, N, V, sh, geo, NT, dim3(sh.Gv, sh.tiles), stream,
            (RhsState *)(base + st_off), (double2 *)(base + part_off)};
-    const dim3 grid(sh.G, (N + NT - 1) / NT);
+    const dim3 grid(sh.Gv, sh.tiles);
     if (!P.x0_is_guess) WDT_HIP(hipMemsetAsync(x, 0, vb64, stream));
     std::vector<RhsState> hs(N);
     std::vector<int> hmask(N);
@@ -511,8 +583,8 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
         for (int k = 0; k < N; ++k) outer[k] += hmask[k];
         WDT_HIP(hipMemcpyAsync(mask, hmask.data(), sizeof(int) * N, hipMemcpyHostToDevice, stream));
         // inner system D e = r (low precision), e = 0, rhat = r
-        hipLaunchKernelGGL((k_convert<F64, S, false>), grid, dim3(sh.threads), 0, stream, V, N, NT,
-                           sh.SB, sh.chunk, sp<F64>(r64, V, N), sp<S>(rS, V, N));
+        hipLaunchKernelGGL((k_convert<F64, S, false>), grid, dim3(sh.threads), 0, stream, geo, N, NT,
+                           sh.SB, sp<F64>(r64, V, N), sp<S>(rS, V, N));
         WDT_HIP(hipMemsetAsync(e, 0, vbl, stream));
         // ||r||^2 in the stored precision: residual of e = 0 against rS
         WDT_TRY(launch_dslash(g, m0, prec, 0, EPI_RESID, e, rhat, rS, N, B.part, sh, stream));
@@ -530,8 +602,8 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
         for (int k = 0; k < N; ++k) total_it[k] += hs[k].iters - before[k];
         budget -= done;
         // x += e
-        hipLaunchKernelGGL((k_convert<S, F64, true>), grid, dim3(sh.threads), 0, stream, V, N, NT,
-                           sh.SB, sh.chunk, sp<S>(e, V, N), sp<F64>(x, V, N));
+        hipLaunchKernelGGL((k_convert<S, F64, true>), grid, dim3(sh.threads), 0, stream, geo, N, NT,
+                           sh.SB, sp<S>(e, V, N), sp<F64>(x, V, N));
         WDT_HIP(hipGetLastError());
     }
     (void)rc;

@@ -11,7 +11,8 @@ import re
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libwdt.so")
+# WDT_LIB selects another build of the library (A/B timing of build options)
+LIB_PATH = os.environ.get("WDT_LIB") or os.path.join(HERE, "libwdt.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "wdt.h")
 
 OK, WNOTCONVERGED, EINVAL, ENOMEM, EHIP, ESEARCH, ENODEVICE = 0, 1, -1, -2, -3, -4, -5
@@ -304,3 +305,12 @@ def profile_read():
         out[e.name.decode()] = dict(calls=int(e.calls), ms=e.ms, bytes=e.bytes,
                                     gbps=(e.bytes / (e.ms * 1e-3) / 1e9) if e.ms > 0 else 0.0)
     return out
+
+
+def set_launch_shape(rhs_tile=0, sites_per_block=0, max_blocks=0, z_slab=0):
+    """Override the launch shape of the (site, rhs) kernels (0 = automatic)."""
+    L = lib()
+    L.wdt_set_launch_shape.restype = ctypes.c_int
+    L.wdt_set_launch_shape.argtypes = [ctypes.c_int32] * 4
+    check(L.wdt_set_launch_shape(rhs_tile, sites_per_block, max_blocks, z_slab),
+          "wdt_set_launch_shape")
