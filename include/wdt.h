@@ -211,6 +211,14 @@ int wdt_force(wdt_gauge g, const void *dev_x, const void *dev_y, int32_t n_rhs,
               const double *grad_out, void *dev_grad_U, double *grad_m0, void *stream);
 
 /*
+ * dev_out = gamma5 dev_in for an FP64 batch (gamma5 = diag(1, 1, -1, -1) on the
+ * spin index).  With the Hermiticity of Gamma5 D (Sec. 2) this gives the
+ * adjoint solution D^-dag eta = gamma5 D^-1 (gamma5 eta) from an ordinary
+ * solve.  dev_in may equal dev_out.
+ */
+int wdt_gamma5(wdt_lattice lat, const void *dev_in, void *dev_out, int32_t n_rhs, void *stream);
+
+/*
  * Layout bridge between the natural order [n_rhs][V][12] (complex double)
  * and the batch layout [V][12][n_rhs] used above (FP64 only).
  */

@@ -462,3 +462,30 @@ int wdt_force(wdt_gauge g, const void *dev_x, const void *dev_y, int32_t n_rhs,
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// out = gamma5 in (DeGrand-Rossi gamma5 = diag(1, 1, -1, -1) on spins), FP64
+// batches; with D^dag = gamma5 D gamma5 (Sec. 2: Q = Gamma5 D is Hermitian)
+// it turns a solve with D into one with D^dag: D^-dag eta = g5 D^-1 g5 eta.
+namespace wdt {
+__global__ void k_gamma5(const double2 *__restrict__ in, double2 *__restrict__ out, int64_t V,
+                         int N) {
+    const int64_t n = V * 12 * N;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)((i / N) % 12);
+        const double2 v = in[i];
+        out[i] = (k >= 6) ? make_double2(-v.x, -v.y) : v;
+    }
+}
+}  // namespace wdt
+
+extern "C" int wdt_gamma5(wdt_lattice lat, const void *dev_in, void *dev_out, int32_t n_rhs,
+                          void *stream) {
+    using namespace wdt;
+    WDT_CHECK(lat && dev_in && dev_out && n_rhs >= 1, "wdt_gamma5: bad argument");
+    hipLaunchKernelGGL(k_gamma5, dim3(2048), dim3(256), 0, (hipStream_t)stream,
+                       (const double2 *)dev_in, (double2 *)dev_out, lat->V, n_rhs);
+    WDT_HIP(hipGetLastError());
+    return WDT_OK;
+}

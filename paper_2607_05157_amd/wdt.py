@@ -78,6 +78,7 @@ def lib():
             "wdt_contract": (ctypes.c_int, [vp, vp, vp, i32, P(dbl), i32, P(dbl), vp]),
             "wdt_force": (ctypes.c_int, [vp, vp, vp, i32, P(dbl), vp, P(dbl), vp]),
             "wdt_pack_spinor": (ctypes.c_int, [vp, vp, vp, i32, vp]),
+            "wdt_gamma5": (ctypes.c_int, [vp, vp, vp, i32, vp]),
             "wdt_unpack_spinor": (ctypes.c_int, [vp, vp, vp, i32, vp]),
         }
         for name, (res, args) in sig.items():
@@ -261,6 +262,13 @@ def force(gauge, x, y, n_rhs, grad_out, grad_U, stream=None):
                           ctypes.c_void_p(grad_U.data_ptr()), ctypes.byref(gm), _stream(stream)),
           "wdt_force")
     return gm.value
+
+
+def gamma5(lat, x, out, n_rhs, stream=None):
+    """out = gamma5 x for an FP64 batch (in place allowed)."""
+    check(lib().wdt_gamma5(lat.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                           n_rhs, _stream(stream)), "wdt_gamma5")
+    return out
 
 
 def pack(lat, natural, batch, n_rhs, stream=None):

@@ -1,0 +1,176 @@
+"""GPU checks of the estimator driver (probing x dilution, correlator,
+checkpoint/resume) and of the differentiable trace (forward, backward, finite
+differences), against the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import colouring, dirac, estimator as oest, force as oforce, gamma, noise
+from oracle import solve as osolve
+from synth.gauge import gauge_field
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+W = E = None
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    global W, E
+    from paper_2607_05157_amd import wdt, estimator
+    W, E = wdt, estimator
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    wdt.init(0)
+    yield
+
+
+def _oracle_probing(dims, U, m0, d, t0, seeds, correlator=False):
+    V = int(np.prod(dims))
+    Dinv = osolve.dense_inverse(dirac.dense_D(U, m0, dims, -1))
+    nc, sig = colouring.search(dims, d)
+    col = colouring.colours(dims, sig, nc)
+    per_seed, corr = [], []
+    for s in seeds:
+        tot, C = 0j, np.zeros(dims[3])
+        for j in range(nc):
+            for k in range(12):
+                v = noise.probing_vector(dims, s, col, j, k, t0)
+                if not v.any():
+                    continue
+                x = (Dinv @ v.ravel()).reshape(V, 12)
+                tot += oest.sample_dot(v, x, dims, t0, gamma.GAMMA5)
+                C += oest.sample_norm2_per_t(x, dims)
+        per_seed.append(tot)
+        corr.append(C)
+    return np.array(per_seed), np.array(corr), Dinv, nc, sig
+
+
+@pytest.mark.parametrize("prec,tol,bar", [("fp64", 1e-12, 1e-10), ("fp16", 1e-10, 1e-8)])
+def test_probing_loop_matches_oracle(prec, tol, bar):
+    dims, m0, t0, seeds = (4, 4, 4, 4), 0.2, 1, [0, 1, 2]
+    say("probing loop", dims, prec)
+    U = gauge_field(dims, 0.3, seed=1)
+    ref, refC, Dinv, nc, sig = _oracle_probing(dims, U, m0, 2, t0, seeds, correlator=True)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    p = W.FP64 if prec == "fp64" else W.FP16
+    out = E.probing_loop(g, lat, m0, nc, sig, t0, seeds, n_rhs=40, tol=tol, prec=p,
+                         correlator=True)
+    scale = np.max(np.abs(ref)) + np.sum(np.abs(ref)) / len(ref)
+    assert np.max(np.abs(out["per_seed"] - ref)) < bar * max(scale, 1.0)
+    assert np.max(np.abs(out["correlator_per_seed"] - refC)) < bar * np.max(refC)
+    # the exact loop is within a few standard errors of the estimate
+    exact = oest.exact_loop(Dinv, dims, t0).real
+    assert abs(out["estimate"].real - exact) < 6 * np.sqrt(out["var_seeds"] / len(seeds)) + 1e-6
+
+
+def test_probing_checkpoint_resume(tmp_path):
+    dims, m0, t0, seeds = (4, 4, 4, 4), 0.2, 0, [3, 4]
+    say("checkpoint resume")
+    U = gauge_field(dims, 0.3, seed=1)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    nc, sig = W.colouring_search(dims, 1)
+    ck = str(tmp_path / "ck.jsonl")
+    part = E.probing_loop(g, lat, m0, nc, sig, t0, seeds, n_rhs=16, prec=W.FP64, tol=1e-12,
+                          checkpoint=ck, max_batches=1)
+    assert len(open(ck).readlines()) == 1
+    full = E.probing_loop(g, lat, m0, nc, sig, t0, seeds, n_rhs=16, prec=W.FP64, tol=1e-12,
+                          checkpoint=ck)
+    fresh = E.probing_loop(g, lat, m0, nc, sig, t0, seeds, n_rhs=16, prec=W.FP64, tol=1e-12)
+    assert len(open(ck).readlines()) == (full["n_jobs"] + 15) // 16
+    assert np.allclose(full["per_seed"], fresh["per_seed"], rtol=0, atol=1e-12)
+    assert not np.allclose(part["per_seed"], fresh["per_seed"])
+
+
+def test_traceloss_matches_dense_oracle():
+    dims, m0, N = (4, 4, 2, 4), 0.15, 4
+    say("TraceLoss dense oracle", dims)
+    V = int(np.prod(dims))
+    U = gauge_field(dims, 0.4, seed=31)
+    lat = W.Lattice(dims, -1)
+    eta = lat.new_batch(N)
+    W.sources(lat, W.source_descs(list(range(10, 10 + N))), eta)
+    Ut = torch.tensor(U, requires_grad=True)
+    mt = torch.tensor(m0, dtype=torch.float64, requires_grad=True)
+    f = E.TraceLoss.apply(Ut, mt, lat, eta, 1e-13)
+    gout = torch.tensor([1.0, 1j, 0.5 - 0.25j, -1.0 + 2j], dtype=torch.complex128)
+    f.backward(gout)
+    D = dirac.dense_D(U, m0, dims, -1)
+    Eh = eta.cpu().numpy().reshape(-1, N)
+    X = osolve.dense_solve(D, Eh)
+    Y = osolve.dense_solve(D.conj().T, Eh)
+    fo = np.einsum("ik,ik->k", np.conj(Eh), X)
+    assert np.max(np.abs(f.detach().numpy() - fo)) < 1e-10 * np.max(np.abs(fo))
+    gU = oforce.grad_links([X[:, k] for k in range(N)], [Y[:, k] for k in range(N)],
+                           gout.numpy(), dims, -1)
+    gm = oforce.grad_m0([X[:, k] for k in range(N)], [Y[:, k] for k in range(N)], gout.numpy())
+    assert np.max(np.abs(Ut.grad.numpy() - gU)) < 1e-9 * np.max(np.abs(gU))
+    assert abs(mt.grad.item() - gm) < 1e-9 * abs(gm)
+
+
+def test_traceloss_finite_differences_8x4():
+    """8^4, 8 Rademacher vectors: d/dm0 and 20 random link derivatives of
+    sum_k f_k against central differences with h = 1e-6.  f(U +- hE) - f(U)
+    is computed by defect correction (solve (D + dD) dx = -dD x), which keeps
+    the O(h) difference accurate to the solver tolerance."""
+    dims, m0, N, h = (8, 8, 8, 8), 0.2, 8, 1e-6
+    say("TraceLoss finite differences", dims)
+    V = int(np.prod(dims))
+    U = gauge_field(dims, 0.3, seed=4)
+    lat = W.Lattice(dims, -1)
+    eta = lat.new_batch(N)
+    W.sources(lat, W.source_descs(list(range(N))), eta)
+    Ut = torch.tensor(U, requires_grad=True)
+    mt = torch.tensor(m0, dtype=torch.float64, requires_grad=True)
+    f = E.TraceLoss.apply(Ut, mt, lat, eta, 1e-13)
+    f.sum().real.backward()             # gradient of Re sum_k f_k
+    gU = Ut.grad.numpy()
+    gm = mt.grad.item()
+    g0 = W.Gauge(lat, U)
+    x = lat.new_batch(N)
+    W.solve(g0, m0, eta, x, N, tol=1e-13)
+    xh = x.cpu().numpy()
+    eh = eta.cpu().numpy()
+
+    def delta_f(U2, m2, sites):
+        # (D' - D) x at the affected sites, then dx = -(D')^-1 (D' - D) x
+        if sites is None:                  # mass shift: D' - D = (m2 - m0) 1
+            dDx = (m2 - m0) * xh
+        else:
+            dDx = np.zeros_like(xh)
+            a = dirac.apply_D_sites(U2, m2, xh, dims, sites, -1)
+            b0 = dirac.apply_D_sites(U, m0, xh, dims, sites, -1)
+            dDx[sites] = a - b0
+        rhs = torch.from_numpy(-dDx).cuda()
+        g2 = W.Gauge(lat, U2)
+        dx = lat.new_batch(N)
+        W.solve(g2, m2, rhs, dx, N, tol=1e-11)
+        return np.sum(np.conj(eh) * dx.cpu().numpy())
+
+    fdm = (delta_f(U, m0 + h, None) - delta_f(U, m0 - h, None)) / (2 * h)
+    assert abs(fdm.real - gm) < 1e-5 * abs(gm)
+    rng = np.random.default_rng(7)
+    strides = [1, 8, 64, 512]
+    for _ in range(20):
+        s, mu, a, b = int(rng.integers(V)), int(rng.integers(4)), int(rng.integers(3)), int(rng.integers(3))
+        c = [(s // strides[i]) % 8 for i in range(4)]
+        c[mu] = (c[mu] + 1) % 8
+        nbr = sum(c[i] * strides[i] for i in range(4))
+        sites = [s, nbr]
+        for unit in (1.0, 1j):
+            Ep = U.copy()
+            Em = U.copy()
+            Ep[s, mu, a, b] += unit * h
+            Em[s, mu, a, b] -= unit * h
+            fd = (delta_f(Ep, m0, sites) - delta_f(Em, m0, sites)) / (2 * h)
+            # d Re(sum f) / d Re U = Re(grad), d / d Im U = Im(grad) (torch convention)
+            want = gU[s, mu, a, b].real if unit == 1.0 else gU[s, mu, a, b].imag
+            assert abs(fd.real - want) < 2e-5 * max(abs(want), 1e-2), (s, mu, a, b, unit, fd, want)
