@@ -51,6 +51,55 @@ def cpu_baseline(U, m0, dims, b_host, n_rhs):
                        f"runs on one thread (host has {len(os.sched_getaffinity(0))} cores)")
 
 
+def batched_leg(log, n_per_shape=32):
+    """The uneven workload: 8^4, 8^3x16 and 12^3x24 instances (n_per_shape
+    each) with seeded eps, m0 and 16..48 Rademacher RHS, FP64 to 1e-10, solved
+    as one graph-replayed batch (after a short plan tuning) and as one solve
+    per system."""
+    import torch
+    from synth.gauge import gauge_field
+    from synth.workloads import batched_instances
+    from paper_2607_05157_amd import wdt
+    inst = batched_instances(n_per_shape=n_per_shape)
+    systems = []
+    for i in inst:
+        lat = wdt.Lattice(i["dims"], -1)
+        g = wdt.Gauge(lat, gauge_field(i["dims"], i["eps"], i["gauge_seed"]))
+        b = lat.new_batch(i["n_rhs"])
+        wdt.sources(lat, wdt.source_descs([i["noise_seed_base"] + k for k in range(i["n_rhs"])]), b)
+        systems.append(dict(lat=lat, g=g, b=b, x=lat.new_batch(i["n_rhs"]), m0=i["m0"], N=i["n_rhs"]))
+    log("batched leg:", len(systems), "systems")
+    B = wdt.Batch([s["g"] for s in systems], [s["m0"] for s in systems], [s["N"] for s in systems])
+    untuned = B.info()
+    ms_it = B.tune(iters=3)
+    plan = B.info()
+    B.solve([s["b"] for s in systems], [s["x"] for s in systems], tol=1e-10)   # warm
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rc, st = B.solve([s["b"] for s in systems], [s["x"] for s in systems], tol=1e-10)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t
+    del B
+    for s in systems[:3]:
+        wdt.solve(s["g"], s["m0"], s["b"], s["x"], s["N"], tol=1e-10)      # warm
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st1 = []
+    for s in systems:
+        _, stt = wdt.solve(s["g"], s["m0"], s["b"], s["x"], s["N"], tol=1e-10)
+        st1.extend(stt)
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t
+    return {"systems": len(systems), "total_rhs": sum(s["N"] for s in systems),
+            "seconds_batched_graph": round(t_batched, 4),
+            "seconds_one_solve_per_system": round(t_single, 4),
+            "speedup": round(t_single / t_batched, 3),
+            "tuned_plan": plan, "untuned_plan": untuned, "tuned_ms_per_iteration": round(ms_it, 4),
+            "max_true_residual_batched": max(x["true_residual"] for x in st),
+            "max_true_residual_single": max(x["true_residual"] for x in st1),
+            "iterations_max": max(x["iterations"] for x in st)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +108,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--inner-tol", type=float, default=0.05)
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the trace estimate "
@@ -146,6 +196,10 @@ def main():
     iters = [s["iterations"] for st in stats for s in st]
     outer = [s["outer"] for st in stats for s in st]
 
+    batched = None
+    if not args.no_batched:
+        batched = batched_leg(log)
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle)")
@@ -185,6 +239,7 @@ def main():
         "solver": {"max_true_residual": max_res, "iterations_max": max(iters),
                    "outer_max": max(outer),
                    "fp64_iterations_max": max(s["iterations"] for st in st64 for s in st)},
+        "batched_uneven_workload": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -179,6 +179,28 @@ int wdt_solve(wdt_gauge g, double m0, const void *dev_b, void *dev_x, int32_t n_
               const wdt_solve_params *params, wdt_rhs_stats *stats, void *stream);
 
 /*
+ * Many uneven systems solved together (FP64 BiCGStab, same recurrence and
+ * stopping rule as wdt_solve): system i has its own lattice and links
+ * (gauges[i]), mass m0[i] and n_rhs[i] right-hand sides.  Every phase of an
+ * iteration is one launch over all systems, and one iteration is replayed
+ * from a captured hipGraph on a stream the batch owns (ordered after and
+ * before the caller's stream).  The gauge handles must outlive the batch.
+ * wdt_batch_tune times candidate block budgets and RHS tiles for `iters`
+ * iterations and keeps the fastest plan (*best_ms: time per iteration).
+ * wdt_batch_solve: dev_b[i], dev_x[i] are FP64 batches of system i; stats
+ * (may be NULL) receives sum(n_rhs) records, systems in order.
+ */
+typedef struct wdt_batch_s *wdt_batch;
+int wdt_batch_create(const wdt_gauge *gauges, const double *m0, const int32_t *n_rhs,
+                     int32_t n_sys, wdt_batch *out);
+int wdt_batch_destroy(wdt_batch b);
+int wdt_batch_tune(wdt_batch b, int32_t iters, double *best_ms);
+int wdt_batch_solve(wdt_batch b, void *const *dev_b, void *const *dev_x,
+                    const wdt_solve_params *params, wdt_rhs_stats *stats, void *stream);
+/* Plan in use: total blocks per launch, block budget per CU, largest RHS tile. */
+int wdt_batch_info(wdt_batch b, int32_t *total_blocks, int32_t *blocks_per_cu, int32_t *tile_cap);
+
+/*
  * Contractions of a source batch v and a solution batch x (FP64 batches).
  * mode WDT_CONTRACT_DOT: host_out[r][t] (complex, 2 doubles) =
  *     sum_{x in slice t} sum_{s,s',c} conj(v_r(x,s,c)) B_{s s'} x_r(x,s',c)

@@ -318,23 +318,26 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
-// Loop of a (site, rhs) kernel: thread (rl, ry) of a block of NT*SB threads
-// handles RHS blockIdx.y*NT + rl and position ry of each group of SB
-// consecutive processing positions the block's sweep visits.  Expects a Geom
-// g and N, NT, SB in scope.
-#define SITE_LOOP_BEGIN                                                    \
+// Loop of a (site, rhs) kernel body: thread (rl, ry) of a block of NT*SB
+// threads handles RHS TILE*NT + rl and position ry of each group of SB
+// consecutive processing positions that logical block LB of GB visits.
+// Expects a Geom g and N, NT, SB in scope.
+#define SITE_LOOP_BEGIN_AT(TILE, LB, GB)                                   \
     const int tid = threadIdx.x;                                           \
     const int rl = tid % NT;                                               \
     const int ry = tid / NT;                                               \
-    const int r = blockIdx.y * NT + rl;                                    \
+    const int r = (TILE) * NT + rl;                                        \
     const bool live = (ry < SB) && (r < N);                                \
-    const int Lb = xcd_block(blockIdx.x, gridDim.x);                       \
-    const Sweep sw_ = sweep((g.V + SB - 1) / SB, Lb, gridDim.x);           \
+    const int Lb = (LB);                                                   \
+    const int Gb = (GB);                                                   \
+    const Sweep sw_ = sweep((g.V + SB - 1) / SB, Lb, Gb);                  \
     if (live)                                                              \
         for (int grp = sw_.first; grp < sw_.end; grp += sw_.step) {        \
             const int p_ = grp * SB + ry;                                  \
             if (p_ >= g.V) break;                                          \
             const int s = site_of(g, p_);
+
+#define SITE_LOOP_BEGIN SITE_LOOP_BEGIN_AT(blockIdx.y, xcd_block(blockIdx.x, gridDim.x), gridDim.x)
 
 #define SITE_LOOP_END }
 

@@ -22,163 +22,20 @@
 //
 // Optional epilogues fuse the per-RHS dot products BiCGStab needs right after
 // an operator application, so the output is not read back from memory.
-#include "internal.h"
+#include "kernels.h"
 
 #include <map>
 #include <type_traits>
 
 namespace wdt {
 
-// Empty asm that claims to modify the accumulator: it makes the hops before
-// it complete before later hops start.  Without it the compiler sinks all
-// accumulation to the end of the site and keeps every neighbour's spinor and
-// link live at once (hundreds of VGPRs, spills); with one after every hop it
-// serialises the loads.  PIN = 1 places it after each direction (two hops
-// whose loads are issued together), PIN = 2 after each hop.
-template <class T>
-__device__ __forceinline__ void pin(cplx<T> (&a)[12]) {
-#pragma unroll
-    for (int k = 0; k < 12; ++k) asm volatile("" : "+v"(a[k].re), "+v"(a[k].im));
-}
-
-// Schedule per precision: one direction (two spinors, two links) in flight.
-template <class S> struct OpPin { static constexpr int value = 1; };
-
-// Non-temporal output stores keep the operator's output from evicting input
-// lines that neighbouring sites still have to re-read from L2.
-#ifndef WDT_OP_STREAM_STORES
-#define WDT_OP_STREAM_STORES 1
-#endif
-
-template <int MU, bool DAG, int PIN, int NC, class S>
-__device__ __forceinline__ void hop_pair(const Geom &g, const typename S::link *__restrict__ U,
-                                         const SpinorPtr<S> &in, int s, const SiteNbr &nb, int r,
-                                         cplx<typename S::real> (&acc)[12]) {
-    using R = typename S::real;
-    constexpr int SF = DAG ? +1 : -1;  // forward projector (1 + SF gamma_mu)
-    const int b = nb.bwd[MU];
-    cplx<R> pf[12], pb[12], uf[9], ub[9];
-    R sf = load_site_raw<S, NC>(in, nb.fwd[MU], r, pf);
-    load_link<S, R>(U, s, MU, uf);
-    R sb = R(1);
-    if constexpr (PIN != 2) {
-        sb = load_site_raw<S, NC>(in, b, r, pb);
-        load_link<S, R>(U, b, MU, ub);
-    }
-    {
-        // the FP16 scale and the time-boundary sign act on the half spinor
-        if (MU == 3 && nb.fwd_wrap_t && g.bc_t < 0) sf = -sf;
-        cplx<R> h[6];
-        project<MU, SF>(pf, h);
-        if constexpr (S::scaled || MU == 3) {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) h[k] = {h[k].re * sf, h[k].im * sf};
-        }
-        cplx<R> w[6];
-        su3_mul(uf, h, w);
-        reconstruct_add<MU, SF>(acc, w);
-    }
-    if constexpr (PIN == 2) {
-        pin(acc);
-        sb = load_site_raw<S, NC>(in, b, r, pb);
-        load_link<S, R>(U, b, MU, ub);
-    }
-    {
-        if (MU == 3 && nb.bwd_wrap_t && g.bc_t < 0) sb = -sb;
-        cplx<R> h[6];
-        project<MU, -SF>(pb, h);
-        if constexpr (S::scaled || MU == 3) {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) h[k] = {h[k].re * sb, h[k].im * sb};
-        }
-        cplx<R> w[6];
-        su3_adj_mul(ub, h, w);
-        reconstruct_add<MU, -SF>(acc, w);
-    }
-    if constexpr (PIN != 0) pin(acc);
-}
-
 template <class S, int NC, bool DAG, int EPI>
 __global__ __launch_bounds__(256) void k_dslash(Geom g, const typename S::link *__restrict__ U,
                                                 typename S::real diag, SpinorPtr<S> in,
                                                 SpinorPtr<S> out, SpinorPtr<S> aux, int N, int NT,
                                                 int SB, double2 *__restrict__ partials) {
-    using R = typename S::real;
-    constexpr int PIN = OpPin<S>::value;
-    __shared__ double2 red[2][256];
-    const int tid = threadIdx.x;
-    const int rl = tid % NT;
-    const int ry = tid / NT;
-    const int r = blockIdx.y * NT + rl;
-    const bool live = (ry < SB) && (r < N);
-    const int Lb = xcd_block(blockIdx.x, gridDim.x);
-    const Sweep sw = sweep((g.V + SB - 1) / SB, Lb, gridDim.x);
-    double d0r = 0, d0i = 0, d1r = 0, d1i = 0;
-    if (live) {
-        for (int grp = sw.first; grp < sw.end; grp += sw.step) {
-            const int p = grp * SB + ry;
-            if (p >= g.V) break;
-            const int s = site_of(g, p);
-            const SiteNbr nb = neighbours(g, s);
-            cplx<R> acc[12];
-#pragma unroll
-            for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
-            hop_pair<0, DAG, PIN, NC, S>(g, U, in, s, nb, r, acc);
-            hop_pair<1, DAG, PIN, NC, S>(g, U, in, s, nb, r, acc);
-            hop_pair<2, DAG, PIN, NC, S>(g, U, in, s, nb, r, acc);
-            hop_pair<3, DAG, PIN, NC, S>(g, U, in, s, nb, r, acc);
-            cplx<R> c[12];
-            load_site<S, NC>(in, s, r, c);
-            cplx<R> o[12];
-#pragma unroll
-            for (int k = 0; k < 12; ++k)
-                o[k] = {diag * c[k].re - R(0.5) * acc[k].re, diag * c[k].im - R(0.5) * acc[k].im};
-            if constexpr (EPI == EPI_RESID) {
-                cplx<R> b[12];
-                load_site<S, NC>(aux, s, r, b);
-#pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    o[k] = csub(b[k], o[k]);
-                    d0r += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
-                    d1r += (double)b[k].re * b[k].re + (double)b[k].im * b[k].im;
-                }
-            } else if constexpr (EPI == EPI_DOT_AUX) {
-                cplx<R> a[12];
-                load_site<S, NC>(aux, s, r, a);
-#pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    d0r += (double)a[k].re * o[k].re + (double)a[k].im * o[k].im;
-                    d0i += (double)a[k].re * o[k].im - (double)a[k].im * o[k].re;
-                }
-            } else if constexpr (EPI == EPI_DOT_TS) {
-#pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    d0r += (double)o[k].re * c[k].re + (double)o[k].im * c[k].im;
-                    d0i += (double)o[k].re * c[k].im - (double)o[k].im * c[k].re;
-                    d1r += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
-                }
-            }
-            store_site<S, WDT_OP_STREAM_STORES != 0, NC>(out, s, r, o);
-        }
-    }
-    if constexpr (EPI != EPI_NONE) {
-        red[0][tid] = make_double2(d0r, d0i);
-        red[1][tid] = make_double2(d1r, d1i);
-        __syncthreads();
-        if (ry == 0 && r < N) {
-            double2 s0 = red[0][rl], s1 = red[1][rl];
-            for (int y = 1; y < SB; ++y) {
-                const double2 a0 = red[0][y * NT + rl], a1 = red[1][y * NT + rl];
-                s0.x += a0.x;
-                s0.y += a0.y;
-                s1.x += a1.x;
-                s1.y += a1.y;
-            }
-            const int Gt = gridDim.x;
-            partials[((size_t)0 * Gt + Lb) * N + r] = s0;
-            if (EPI != EPI_DOT_AUX) partials[((size_t)1 * Gt + Lb) * N + r] = s1;
-        }
-    }
+    dslash_body<S, NC, DAG, EPI>(g, U, diag, in, out, aux, N, NT, SB, partials, blockIdx.y,
+                                 xcd_block(blockIdx.x, gridDim.x), gridDim.x);
 }
 
 // Batch sizes with a compiled-in constant (other sizes use the runtime path).

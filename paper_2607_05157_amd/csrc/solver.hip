@@ -13,255 +13,53 @@
 // per-block dot partials into alpha, omega, beta and the convergence flags, so
 // the host only polls the flags every `check_every` iterations.  All sums use
 // a fixed order, so results are bit-reproducible run to run.
-#include "internal.h"
-
 #include <algorithm>
 #include <cmath>
 
+#include "kernels.h"
+
 namespace wdt {
 
-struct RhsState {
-    double2 rho, alpha, omega, beta;
-    double rr, bb, tol2;
-    int active;  // 1 while the RHS is iterating
-    int flag;    // 0 running, 1 converged, 2 breakdown
-    int iters;
-    int pad;
-};
-
-__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
-    const double d = b.x * b.x + b.y * b.y;
-    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
-}
-__device__ __forceinline__ double2 cmuld(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
-// Sum partials[(d*G + i)*N + r] over i in a fixed order (one block per RHS).
-__device__ double2 block_sum(const double2 *__restrict__ partials, int d, int G, int N, int r) {
-    __shared__ double2 sm[256];
-    double2 acc = make_double2(0, 0);
-    for (int i = threadIdx.x; i < G; i += blockDim.x) {
-        const double2 p = partials[((size_t)d * G + i) * N + r];
-        acc.x += p.x;
-        acc.y += p.y;
-    }
-    sm[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            sm[threadIdx.x].x += sm[threadIdx.x + w].x;
-            sm[threadIdx.x].y += sm[threadIdx.x + w].y;
-        }
-        __syncthreads();
-    }
-    const double2 out = sm[0];
-    __syncthreads();
-    return out;
-}
-
-// After r = b - D x: rr = ||r||^2, bb = ||b||^2; start the recurrence with
-// rhat = r.  `bb_ref` (optional) supplies the norm the tolerance refers to.
 __global__ void k_init_state(RhsState *st, const double2 *partials, int G, int N, double tol,
                              const int *mask) {
-    const int r = blockIdx.x;
-    const double2 rr = block_sum(partials, 0, G, N, r);
-    const double2 bb = block_sum(partials, 1, G, N, r);
-    if (threadIdx.x == 0) {
-        RhsState s = st[r];
-        s.rr = rr.x;
-        s.bb = bb.x;
-        s.tol2 = tol * tol;
-        s.rho = make_double2(rr.x, 0.0);
-        s.alpha = make_double2(0, 0);
-        s.omega = make_double2(0, 0);
-        s.beta = make_double2(0, 0);
-        const bool want = (mask == nullptr) || mask[r];
-        const bool done = !(rr.x > s.tol2 * bb.x);
-        s.active = (want && !done) ? 1 : 0;
-        s.flag = done ? 1 : 0;
-        st[r] = s;
-    }
+    init_state_body(st, partials, G, N, tol, mask, blockIdx.x);
 }
-
 __global__ void k_scalar_alpha(RhsState *st, const double2 *partials, int G, int N) {
-    const int r = blockIdx.x;
-    const double2 rv = block_sum(partials, 0, G, N, r);
-    if (threadIdx.x == 0) {
-        RhsState s = st[r];
-        if (s.active) {
-            if (rv.x == 0.0 && rv.y == 0.0) {
-                s.active = 0;
-                s.flag = 2;
-                s.alpha = make_double2(0, 0);
-            } else {
-                s.alpha = cdiv(s.rho, rv);
-            }
-        } else {
-            s.alpha = make_double2(0, 0);
-        }
-        st[r] = s;
-    }
+    scalar_alpha_body(st, partials, G, N, blockIdx.x);
 }
-
 __global__ void k_scalar_omega(RhsState *st, const double2 *partials, int G, int N) {
-    const int r = blockIdx.x;
-    const double2 ts = block_sum(partials, 0, G, N, r);
-    const double2 tt = block_sum(partials, 1, G, N, r);
-    if (threadIdx.x == 0) {
-        RhsState s = st[r];
-        if (s.active && tt.x > 0.0) {
-            s.omega = make_double2(ts.x / tt.x, ts.y / tt.x);
-        } else {
-            s.omega = make_double2(0, 0);
-        }
-        st[r] = s;
-    }
+    scalar_omega_body(st, partials, G, N, blockIdx.x);
 }
-
 __global__ void k_scalar_beta(RhsState *st, const double2 *partials, int G, int N) {
-    const int r = blockIdx.x;
-    const double2 rho_new = block_sum(partials, 0, G, N, r);
-    const double2 rr = block_sum(partials, 1, G, N, r);
-    if (threadIdx.x == 0) {
-        RhsState s = st[r];
-        if (s.active) {
-            s.iters += 1;
-            s.rr = rr.x;
-            if (!(rr.x > s.tol2 * s.bb)) {
-                s.active = 0;
-                s.flag = 1;
-                s.beta = make_double2(0, 0);
-            } else if ((rho_new.x == 0.0 && rho_new.y == 0.0) ||
-                       (s.omega.x == 0.0 && s.omega.y == 0.0) || !isfinite(rr.x)) {
-                s.active = 0;
-                s.flag = 2;
-                s.beta = make_double2(0, 0);
-            } else {
-                s.beta = cmuld(cdiv(rho_new, s.rho), cdiv(s.alpha, s.omega));
-                s.rho = rho_new;
-            }
-        } else {
-            s.beta = make_double2(0, 0);
-        }
-        st[r] = s;
-    }
+    scalar_beta_body(st, partials, G, N, blockIdx.x);
 }
 
-// ---------------------------------------------------------------------------
-// Vector kernels over (site, rhs) with the operator's block shape.
+#define WDT_BLOCK_CTX blockIdx.y, xcd_block(blockIdx.x, gridDim.x), gridDim.x
 
-template <class S> using Rl = typename S::real;
-
-template <class S>
-__device__ __forceinline__ cplx<Rl<S>> to_c(double2 a) {
-    return {(Rl<S>)a.x, (Rl<S>)a.y};
-}
-
-
-
-// s = r - alpha v
 template <class S>
 __global__ __launch_bounds__(256) void k_update_s(Geom g, int N, int NT, int SB,
                                                   const RhsState *__restrict__ st, SpinorPtr<S> rv,
                                                   SpinorPtr<S> vv, SpinorPtr<S> sv) {
-    using R = Rl<S>;
-    SITE_LOOP_BEGIN
-    const cplx<R> a = to_c<S>(st[r].alpha);
-    cplx<R> x[12], y[12];
-    load_site<S>(rv, s, r, x);
-    load_site<S>(vv, s, r, y);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) x[k] = csub(x[k], cmul(a, y[k]));
-    store_site<S>(sv, s, r, x);
-    SITE_LOOP_END
+    update_s_body<S>(g, N, NT, SB, st, rv, vv, sv, WDT_BLOCK_CTX);
 }
-
-// x += alpha p + omega s;  r = s - omega t;  partials: rhat^dag r, ||r||^2
 template <class S>
 __global__ __launch_bounds__(256) void k_update_xr(Geom g, int N, int NT, int SB,
                                                    const RhsState *__restrict__ st, SpinorPtr<S> xv,
                                                    SpinorPtr<S> pv, SpinorPtr<S> sv,
                                                    SpinorPtr<S> tv, SpinorPtr<S> rv,
                                                    SpinorPtr<S> rhat, double2 *partials) {
-    using R = Rl<S>;
-    __shared__ double2 red[2][256];
-    double d0r = 0, d0i = 0, d1r = 0;
-    SITE_LOOP_BEGIN
-    const cplx<R> a = to_c<S>(st[r].alpha);
-    const cplx<R> w = to_c<S>(st[r].omega);
-    cplx<R> x[12], p[12], sv_[12], t[12], h[12];
-    load_site<S>(xv, s, r, x);
-    load_site<S>(pv, s, r, p);
-    load_site<S>(sv, s, r, sv_);
-    load_site<S>(tv, s, r, t);
-    load_site<S>(rhat, s, r, h);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-        x[k] = cadd(x[k], cadd(cmul(a, p[k]), cmul(w, sv_[k])));
-        p[k] = csub(sv_[k], cmul(w, t[k]));  // new r
-        d0r += (double)h[k].re * p[k].re + (double)h[k].im * p[k].im;
-        d0i += (double)h[k].re * p[k].im - (double)h[k].im * p[k].re;
-        d1r += (double)p[k].re * p[k].re + (double)p[k].im * p[k].im;
-    }
-    store_site<S>(xv, s, r, x);
-    store_site<S>(rv, s, r, p);
-    SITE_LOOP_END
-    red[0][tid] = make_double2(d0r, d0i);
-    red[1][tid] = make_double2(d1r, 0.0);
-    __syncthreads();
-    if (ry == 0 && r < N) {
-        double2 s0 = red[0][rl], s1 = red[1][rl];
-        for (int y = 1; y < SB; ++y) {
-            s0.x += red[0][y * NT + rl].x;
-            s0.y += red[0][y * NT + rl].y;
-            s1.x += red[1][y * NT + rl].x;
-        }
-        partials[((size_t)0 * gridDim.x + Lb) * N + r] = s0;
-        partials[((size_t)1 * gridDim.x + Lb) * N + r] = s1;
-    }
+    update_xr_body<S>(g, N, NT, SB, st, xv, pv, sv, tv, rv, rhat, partials, WDT_BLOCK_CTX);
 }
-
-// p = r + beta (p - omega v)
 template <class S>
 __global__ __launch_bounds__(256) void k_update_p(Geom g, int N, int NT, int SB,
                                                   const RhsState *__restrict__ st, SpinorPtr<S> rv,
                                                   SpinorPtr<S> pv, SpinorPtr<S> vv) {
-    using R = Rl<S>;
-    SITE_LOOP_BEGIN
-    const cplx<R> b = to_c<S>(st[r].beta);
-    const cplx<R> w = to_c<S>(st[r].omega);
-    cplx<R> x[12], p[12], v[12];
-    load_site<S>(rv, s, r, x);
-    load_site<S>(pv, s, r, p);
-    load_site<S>(vv, s, r, v);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) p[k] = cadd(x[k], cmul(b, csub(p[k], cmul(w, v[k]))));
-    store_site<S>(pv, s, r, p);
-    SITE_LOOP_END
+    update_p_body<S>(g, N, NT, SB, st, rv, pv, vv, WDT_BLOCK_CTX);
 }
-
-// dst(T) = src(S) converted (and optionally dst += src when ADD)
 template <class SS, class SD, bool ADD>
 __global__ __launch_bounds__(256) void k_convert(Geom g, int N, int NT, int SB,
                                                  SpinorPtr<SS> src, SpinorPtr<SD> dst) {
-    SITE_LOOP_BEGIN
-    cplx<Rl<SS>> a[12];
-    load_site<SS>(src, s, r, a);
-    cplx<Rl<SD>> b[12];
-    if constexpr (ADD) {
-        load_site<SD>(dst, s, r, b);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            b[k].re += (Rl<SD>)a[k].re;
-            b[k].im += (Rl<SD>)a[k].im;
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < 12; ++k) b[k] = {(Rl<SD>)a[k].re, (Rl<SD>)a[k].im};
-    }
-    store_site<SD>(dst, s, r, b);
-    SITE_LOOP_END
+    convert_body<SS, SD, ADD>(g, N, NT, SB, src, dst, WDT_BLOCK_CTX);
 }
 
 // ---------------------------------------------------------------------------

@@ -322,3 +322,59 @@ def set_launch_shape(rhs_tile=0, sites_per_block=0, max_blocks=0, z_slab=0):
     L.wdt_set_launch_shape.argtypes = [ctypes.c_int32] * 4
     check(L.wdt_set_launch_shape(rhs_tile, sites_per_block, max_blocks, z_slab),
           "wdt_set_launch_shape")
+
+
+class Batch:
+    """Several uneven systems solved together (wdt_batch_*).  gauges: Gauge
+    handles (kept alive by this object), m0s and n_rhs per system."""
+
+    def __init__(self, gauges, m0s, n_rhs):
+        L = lib()
+        vp, i32, P = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER
+        L.wdt_batch_create.restype = ctypes.c_int
+        L.wdt_batch_create.argtypes = [P(vp), P(ctypes.c_double), P(i32), i32, P(vp)]
+        L.wdt_batch_destroy.argtypes = [vp]
+        L.wdt_batch_tune.restype = ctypes.c_int
+        L.wdt_batch_tune.argtypes = [vp, i32, P(ctypes.c_double)]
+        L.wdt_batch_solve.restype = ctypes.c_int
+        L.wdt_batch_solve.argtypes = [vp, P(vp), P(vp), P(SolveParams), P(RhsStats), vp]
+        L.wdt_batch_info.restype = ctypes.c_int
+        L.wdt_batch_info.argtypes = [vp, P(i32), P(i32), P(i32)]
+        self.gauges = list(gauges)
+        self.n_rhs = [int(n) for n in n_rhs]
+        n = len(self.gauges)
+        gs = (vp * n)(*[g.h.value for g in self.gauges])
+        ms = (ctypes.c_double * n)(*[float(m) for m in m0s])
+        ns = (i32 * n)(*self.n_rhs)
+        h = vp()
+        check(L.wdt_batch_create(gs, ms, ns, n, ctypes.byref(h)), "wdt_batch_create")
+        self.h = h
+
+    def tune(self, iters=3):
+        ms = ctypes.c_double(0)
+        check(lib().wdt_batch_tune(self.h, iters, ctypes.byref(ms)), "wdt_batch_tune")
+        return ms.value
+
+    def info(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().wdt_batch_info(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+              "wdt_batch_info")
+        return dict(total_blocks=a.value, blocks_per_cu=b.value, tile_cap=c.value)
+
+    def solve(self, bs, xs, tol=1e-10, max_iter=10000, check_every=5, stream=None,
+              allow_unconverged=False):
+        n = len(self.gauges)
+        vb = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
+        vx = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        p = SolveParams(tol, max_iter, FP64, 0.0, 0, 0, check_every)
+        stats = (RhsStats * sum(self.n_rhs))()
+        allow = (OK, WNOTCONVERGED) if allow_unconverged else (OK,)
+        rc = check(lib().wdt_batch_solve(self.h, vb, vx, ctypes.byref(p), stats, _stream(stream)),
+                   "wdt_batch_solve", allow)
+        return rc, [dict(iterations=s.iterations, converged=s.converged, restarts=s.restarts,
+                         true_residual=s.true_residual) for s in stats]
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.wdt_batch_destroy(self.h)
+            self.h = None
