@@ -116,7 +116,8 @@ def batched_leg(log, n_per_shape=32):
             "tuned_plan": plan, "untuned_plan": untuned, "tuned_ms_per_iteration": round(ms_it, 4),
             "max_true_residual_batched": max(x["true_residual"] for x in st),
             "max_true_residual_single": max(x["true_residual"] for x in st1),
-            "iterations_max": max(x["iterations"] for x in st)}
+            "iterations_max": max(x["iterations"] for x in st),
+            "iterations_mean_single": round(sum(x["iterations"] for x in st1) / len(st1), 1)}
 
 
 def main():

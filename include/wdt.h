@@ -271,10 +271,13 @@ typedef struct {
  * sites_per_block = sites a block handles per step, max_blocks = blocks per
  * tile, z_slab = thickness (a divisor of Lz) of the z-slabs of the order in
  * which sites are visited (t-neighbours are Lx*Ly*z_slab sites apart in that
- * order).  0 restores the automatic choice.  Process-wide; not thread-safe.
+ * order), serial_tiles = 1 to have each operator block sweep the RHS tiles
+ * one after the other (0: tiles side by side in the grid).  0 (-1 for
+ * serial_tiles) restores the automatic choice.  Process-wide; not
+ * thread-safe.
  */
 int wdt_set_launch_shape(int32_t rhs_tile, int32_t sites_per_block, int32_t max_blocks,
-                         int32_t z_slab);
+                         int32_t z_slab, int32_t serial_tiles);
 
 int wdt_profile_enable(int on);
 /* Fills up to max entries; *n receives the number of kernel classes. */

@@ -265,7 +265,7 @@ int wdt_gauge_get(wdt_gauge g, double *host_links) {
 }
 
 int wdt_set_launch_shape(int32_t rhs_tile, int32_t sites_per_block, int32_t max_blocks,
-                         int32_t z_slab) {
+                         int32_t z_slab, int32_t serial_tiles) {
     WDT_CHECK(rhs_tile >= 0 && rhs_tile <= 256, "wdt_set_launch_shape: rhs_tile must be 0..256");
     WDT_CHECK(sites_per_block >= 0 && sites_per_block <= 256,
               "wdt_set_launch_shape: sites_per_block must be 0..256");
@@ -273,8 +273,11 @@ int wdt_set_launch_shape(int32_t rhs_tile, int32_t sites_per_block, int32_t max_
     tuning().nt = rhs_tile;
     tuning().sb = sites_per_block;
     WDT_CHECK(z_slab >= 0, "wdt_set_launch_shape: z_slab must be >= 0");
+    WDT_CHECK(serial_tiles >= -1 && serial_tiles <= 1,
+              "wdt_set_launch_shape: serial_tiles must be -1, 0 or 1");
     tuning().gmax = max_blocks;
     tuning().bz = z_slab;
+    tuning().serial = serial_tiles;
     return WDT_OK;
 }
 

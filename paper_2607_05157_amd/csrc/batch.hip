@@ -7,7 +7,11 @@
 //
 // Blocks are dealt to systems in proportion to their work (V * N); each
 // system's range starts at a multiple of 8 blocks, so the XCD-aware
-// renumbering of the single-system kernels carries over unchanged.
+// renumbering of the single-system kernels carries over unchanged.  Systems
+// converge at different iterations: at every convergence check the block
+// budget is dealt again over the systems that still have active RHS (finished
+// ones get none), which only rewrites the device-side system table between
+// graph replays.
 #include "kernels.h"
 
 #include <algorithm>
@@ -63,7 +67,7 @@ __global__ __launch_bounds__(256) void kb_dslash(const SysDesc *sys, int nsys, i
                                                  int aux) {
     WDT_SYS_CTX
     dslash_body<F64, 0, false, EPI>(d.g, d.U, d.diag, sp(in), sp(out), sp(aux >= 0 ? aux : in),
-                                    d.N, d.NT, d.SB, d.part, tile, lb, d.G);
+                                    d.N, d.NT, d.SB, d.part, tile, tile + 1, lb, d.G);
 }
 
 __global__ __launch_bounds__(256) void kb_update_s(const SysDesc *sys, int nsys,
@@ -141,6 +145,9 @@ struct wdt_batch_s {
     SysDesc *dev = nullptr;
     RhsState *st = nullptr;
     int total_rhs = 0, total_blocks = 0;
+    int grid_blocks = 0;    // grid of the captured iteration (>= total_blocks)
+    int cus = 256;
+    std::vector<int> gcap;  // per system: most blocks per tile (partials capacity)
     int blocks_per_cu = 4;  // block budget of the plan (tuned)
     int tile_cap = 16;      // largest RHS tile (tuned)
     void *ws = nullptr;
@@ -157,28 +164,53 @@ int free_plan(wdt_batch_s *b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
+    b->grid_blocks = 0;
     if (b->ws) (void)hipFree(b->ws);
     b->ws = nullptr;
     b->ws_bytes = 0;
     return WDT_OK;
 }
 
-// Lays out shapes, block ranges and workspace for the current tuning values.
+// Deals the block budget over the systems with active[i] != 0, in proportion
+// to V * N, at least 8 blocks per tile, at most gcap; a multiple of 8 each.
+void assign_blocks(wdt_batch_s *b, const std::vector<char> &active) {
+    double work = 0;
+    for (int i = 0; i < b->nsys; ++i)
+        if (active[i]) work += (double)b->gauges[i]->lat.V * b->nrhs[i];
+    const double budget = (double)b->cus * b->blocks_per_cu;
+    int blk = 0;
+    for (int i = 0; i < b->nsys; ++i) {
+        SysDesc &d = b->host[i];
+        d.block_begin = blk;
+        if (!active[i] || work <= 0) {
+            d.G = 8;
+            d.nblocks = 0;
+            continue;
+        }
+        int64_t G = (int64_t)std::llround(budget * (double)b->gauges[i]->lat.V * d.N / work / d.tiles);
+        G = std::max<int64_t>(8, std::min<int64_t>(G, b->gcap[i]));
+        d.G = (int)((G / 8) * 8);
+        d.nblocks = d.tiles * d.G;
+        blk += d.nblocks;
+    }
+    b->total_blocks = blk;
+}
+
+// Lays out shapes and workspace for the current tuning values and deals the
+// blocks over all systems.
 int make_plan(wdt_batch_s *b) {
     WDT_TRY(free_plan(b));
-    int cus = 256;
     {
         int dev = 0;
         hipDeviceProp_t p;
         if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
-            cus = p.multiProcessorCount;
+            b->cus = p.multiProcessorCount;
     }
-    double work = 0;
-    for (int i = 0; i < b->nsys; ++i) work += (double)b->gauges[i]->lat.V * b->nrhs[i];
-    const double budget = (double)cus * b->blocks_per_cu;
+    const double budget = (double)b->cus * b->blocks_per_cu;
     b->host.assign(b->nsys, SysDesc{});
+    b->gcap.assign(b->nsys, 8);
     size_t off = 0;
-    int blk = 0, rhs = 0;
+    int rhs = 0;
     std::vector<size_t> vec_off(b->nsys), part_off(b->nsys);
     for (int i = 0; i < b->nsys; ++i) {
         const wdt_gauge_s *g = b->gauges[i];
@@ -200,26 +232,20 @@ int make_plan(wdt_batch_s *b) {
                 break;
             }
         d.SB = SB;
+        // most blocks this system can get: the whole budget, or one per group
         const int64_t ngroups = (g->lat.V + SB - 1) / SB;
-        int64_t G = (int64_t)std::llround(budget * (double)g->lat.V * N / work / d.tiles);
-        G = std::max<int64_t>(8, std::min<int64_t>(G, ngroups));
-        G = std::max<int64_t>(8, (G / 8) * 8);
-        d.G = (int)G;
-        d.nblocks = d.tiles * d.G;
-        d.block_begin = blk;
-        blk += d.nblocks;
+        int64_t cap = std::min<int64_t>(ngroups, (int64_t)std::ceil(budget / d.tiles));
+        b->gcap[i] = (int)std::max<int64_t>(8, (cap / 8) * 8);
         d.rhs_begin = rhs;
         rhs += N;
-        Geom geo = g->lat.geom();
-        d.g = geo;
+        d.g = g->lat.geom();
         d.U = g->U64;
         d.diag = 4.0 + b->m0[i];
         vec_off[i] = off;
         off += ((size_t)6 * spinor_bytes(g->lat.V, N, WDT_FP64) + 255) / 256 * 256;
         part_off[i] = off;
-        off += ((size_t)2 * d.G * N * sizeof(double2) + 255) / 256 * 256;
+        off += ((size_t)2 * b->gcap[i] * N * sizeof(double2) + 255) / 256 * 256;
     }
-    b->total_blocks = blk;
     b->total_rhs = rhs;
     const size_t st_off = off;
     off += ((size_t)rhs * sizeof(RhsState) + 255) / 256 * 256;
@@ -242,6 +268,7 @@ int make_plan(wdt_batch_s *b) {
     }
     b->st = (RhsState *)(base + st_off);
     b->dev = (SysDesc *)(base + dev_off);
+    assign_blocks(b, std::vector<char>(b->nsys, 1));
     return WDT_OK;
 }
 
@@ -251,9 +278,10 @@ int upload(wdt_batch_s *b) {
     return WDT_OK;
 }
 
-// One BiCGStab iteration for every system (eight launches).
+// One BiCGStab iteration for every system (eight launches over grid_blocks
+// blocks; blocks past the last system's range return at once).
 int enqueue_iteration(wdt_batch_s *b) {
-    const dim3 gb(b->total_blocks), gr(b->total_rhs), t(256);
+    const dim3 gb(b->grid_blocks), gr(b->total_rhs), t(256);
     hipLaunchKernelGGL(kb_dslash<EPI_DOT_AUX>, gb, t, 0, b->stream, b->dev, b->nsys, (int)V_P,
                        (int)V_V, (int)V_RHAT);
     hipLaunchKernelGGL(kb_alpha, gr, t, 0, b->stream, b->dev, b->nsys, b->st);
@@ -268,8 +296,15 @@ int enqueue_iteration(wdt_batch_s *b) {
     return WDT_OK;
 }
 
+// (Re)captures the iteration graph when the current plan needs more blocks
+// than the captured grid has.
 int capture(wdt_batch_s *b) {
-    if (b->exec) return WDT_OK;
+    if (b->exec && b->total_blocks <= b->grid_blocks) return WDT_OK;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->grid_blocks = b->total_blocks;
     WDT_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     const int rc = enqueue_iteration(b);
     hipGraph_t g = nullptr;
@@ -401,6 +436,7 @@ int wdt_batch_solve(wdt_batch b, void *const *dev_b, void *const *dev_x,
     WDT_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     WDT_HIP(hipEventRecord(ev, (hipStream_t)stream));
     WDT_HIP(hipStreamWaitEvent(b->stream, ev, 0));
+    assign_blocks(b, std::vector<char>(b->nsys, 1));
     WDT_TRY(upload(b));
     if (!P->x0_is_guess)
         hipLaunchKernelGGL(kb_copy, dim3(b->total_blocks), dim3(256), 0, b->stream, b->dev,
@@ -410,8 +446,36 @@ int wdt_batch_solve(wdt_batch b, void *const *dev_b, void *const *dev_x,
     const int check = P->check_every > 0 ? P->check_every : 5;
     std::vector<RhsState> hs(b->total_rhs);
     std::vector<int> total_it(b->total_rhs, 0), restarts(b->total_rhs, 0), before(b->total_rhs);
+    const std::vector<char> all(b->nsys, 1);
+    std::vector<char> act(b->nsys, 1), dealt(b->nsys, 1);
+    // which systems still have an active RHS (from the host copy of the states)
+    auto active_systems = [&]() {
+        bool any = false;
+        for (int i = 0; i < b->nsys; ++i) {
+            const SysDesc &d = b->host[i];
+            char a = 0;
+            for (int k = 0; k < d.N; ++k) a |= hs[d.rhs_begin + k].active ? 1 : 0;
+            act[i] = a;
+            any = any || a;
+        }
+        return any;
+    };
+    // deal the blocks over the active systems when that set has changed
+    auto redeal = [&]() -> int {
+        if (act == dealt) return WDT_OK;
+        assign_blocks(b, act);
+        dealt = act;
+        WDT_TRY(upload(b));
+        return capture(b);
+    };
     int budget = P->max_iter, rc = WDT_OK;
     for (int round = 0;; ++round) {
+        // the true residual is taken for every system
+        if (dealt != all) {
+            assign_blocks(b, all);
+            dealt = all;
+            WDT_TRY(upload(b));
+        }
         WDT_TRY(restart(b, P->tol));
         WDT_HIP(hipMemcpyAsync(hs.data(), b->st, sizeof(RhsState) * b->total_rhs,
                                hipMemcpyDeviceToHost, b->stream));
@@ -435,6 +499,8 @@ int wdt_batch_solve(wdt_batch b, void *const *dev_b, void *const *dev_x,
             if (hs[k].active && round > 0) restarts[k] += 1;
             before[k] = hs[k].iters;
         }
+        active_systems();
+        WDT_TRY(redeal());
         int it = 0;
         while (it < budget) {
             WDT_HIP(hipGraphLaunch(b->exec, b->stream));
@@ -443,9 +509,8 @@ int wdt_batch_solve(wdt_batch b, void *const *dev_b, void *const *dev_x,
                 WDT_HIP(hipMemcpyAsync(hs.data(), b->st, sizeof(RhsState) * b->total_rhs,
                                        hipMemcpyDeviceToHost, b->stream));
                 WDT_HIP(hipStreamSynchronize(b->stream));
-                bool act = false;
-                for (auto &s : hs) act = act || s.active;
-                if (!act) break;
+                if (!active_systems()) break;
+                WDT_TRY(redeal());
             }
         }
         WDT_HIP(hipMemcpyAsync(hs.data(), b->st, sizeof(RhsState) * b->total_rhs,

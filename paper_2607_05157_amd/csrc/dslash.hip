@@ -33,8 +33,11 @@ template <class S, int NC, bool DAG, int EPI>
 __global__ __launch_bounds__(256) void k_dslash(Geom g, const typename S::link *__restrict__ U,
                                                 typename S::real diag, SpinorPtr<S> in,
                                                 SpinorPtr<S> out, SpinorPtr<S> aux, int N, int NT,
-                                                int SB, double2 *__restrict__ partials) {
-    dslash_body<S, NC, DAG, EPI>(g, U, diag, in, out, aux, N, NT, SB, partials, blockIdx.y,
+                                                int SB, double2 *__restrict__ partials,
+                                                int serial_tiles) {
+    const int t0 = serial_tiles > 0 ? 0 : (int)blockIdx.y;
+    const int t1 = serial_tiles > 0 ? serial_tiles : t0 + 1;
+    dslash_body<S, NC, DAG, EPI>(g, U, diag, in, out, aux, N, NT, SB, partials, t0, t1,
                                  xcd_block(blockIdx.x, gridDim.x), gridDim.x);
 }
 
@@ -48,9 +51,10 @@ template <class S> static int prec_of() {
 template <class S, int NC, bool DAG, int EPI>
 static void launch_k(dim3 grid, int threads, hipStream_t stream, const Geom &g,
                      const typename S::link *U, typename S::real diag, SpinorPtr<S> pin_,
-                     SpinorPtr<S> pout, SpinorPtr<S> paux, int N, int NT, int SB, double2 *part) {
+                     SpinorPtr<S> pout, SpinorPtr<S> paux, int N, int NT, int SB, double2 *part,
+                     int serial_tiles) {
     hipLaunchKernelGGL((k_dslash<S, NC, DAG, EPI>), grid, dim3(threads), 0, stream, g, U, diag,
-                       pin_, pout, paux, N, NT, SB, part);
+                       pin_, pout, paux, N, NT, SB, part, serial_tiles);
 }
 
 template <class S, bool DAG, int EPI>
@@ -59,7 +63,8 @@ static int launch_t(const wdt_gauge_s *gf, double m0, const void *in, void *out,
                     const typename S::link *U) {
     const Geom g = shaped_geom(gf->lat, sh);
     const int V = g.V;
-    const dim3 grid(sh.G, sh.tiles);
+    const dim3 grid(sh.G, sh.serial ? 1 : sh.tiles);
+    const int serial_tiles = sh.serial ? sh.tiles : 0;
     SpinorPtr<S> pin_ = make_spinor<S>(const_cast<void *>(in), V, N);
     SpinorPtr<S> pout = make_spinor<S>(out, V, N);
     SpinorPtr<S> paux = make_spinor<S>(const_cast<void *>(aux), V, N);
@@ -73,19 +78,19 @@ static int launch_t(const wdt_gauge_s *gf, double m0, const void *in, void *out,
     switch (nc_of(N)) {
         case 16:
             launch_k<S, 16, DAG, EPI>(grid, sh.threads, stream, g, U, diag, pin_, pout, paux, N,
-                                     sh.NT, sh.SB, partials);
+                                     sh.NT, sh.SB, partials, serial_tiles);
             break;
         case 48:
             launch_k<S, 48, DAG, EPI>(grid, sh.threads, stream, g, U, diag, pin_, pout, paux, N,
-                                     sh.NT, sh.SB, partials);
+                                     sh.NT, sh.SB, partials, serial_tiles);
             break;
         case 64:
             launch_k<S, 64, DAG, EPI>(grid, sh.threads, stream, g, U, diag, pin_, pout, paux, N,
-                                     sh.NT, sh.SB, partials);
+                                     sh.NT, sh.SB, partials, serial_tiles);
             break;
         default:
             launch_k<S, 0, DAG, EPI>(grid, sh.threads, stream, g, U, diag, pin_, pout, paux, N,
-                                    sh.NT, sh.SB, partials);
+                                    sh.NT, sh.SB, partials, serial_tiles);
             break;
     }
     WDT_HIP(hipGetLastError());

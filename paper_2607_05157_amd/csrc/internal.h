@@ -97,6 +97,7 @@ struct Shape {
     int G;        // operator blocks per tile (about the number the GPU holds at once)
     int Gv;       // blocks per tile of the vector (BLAS-1) kernels
     int bz, bt;   // processing-order tile (see site_of)
+    bool serial;  // operator blocks sweep the RHS tiles one after the other
 };
 Shape site_shape(const wdt_lattice_s &lat, int N, int prec);
 // Resident blocks per CU of the operator kernel for (prec, N, block size).
@@ -107,6 +108,7 @@ wdt::Geom shaped_geom(const wdt_lattice_s &lat, const Shape &sh);
 // Launch-shape overrides for the tuner (0 = automatic).
 struct LaunchTuning {
     int nt = 0, sb = 0, gmax = 0, bz = 0;
+    int serial = -1;  // RHS tiles one after the other in each block: 1 on, 0 off, -1 automatic
 };
 LaunchTuning &tuning();
 

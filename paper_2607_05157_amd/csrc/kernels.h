@@ -326,17 +326,20 @@ template <class S, int NC, bool DAG, int EPI>
 __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::link *__restrict__ U,
                                             typename S::real diag, SpinorPtr<S> in,
                                             SpinorPtr<S> out, SpinorPtr<S> aux, int N, int NT,
-                                            int SB, double2 *__restrict__ partials, int tile,
-                                            int Lb, int Gb) {
+                                            int SB, double2 *__restrict__ partials, int tile0,
+                                            int tile1, int Lb, int Gb) {
     using R = typename S::real;
     constexpr int PIN = OpPin<S>::value;
     __shared__ double2 red[2][256];
     const int tid = threadIdx.x;
     const int rl = tid % NT;
     const int ry = tid / NT;
+    const Sweep sw = sweep((g.V + SB - 1) / SB, Lb, Gb);
+    // RHS tiles [tile0, tile1) one after the other: the XCD's L2 then holds
+    // one tile's worth of each site instead of the whole batch
+    for (int tile = tile0; tile < tile1; ++tile) {
     const int r = tile * NT + rl;
     const bool live = (ry < SB) && (r < N);
-    const Sweep sw = sweep((g.V + SB - 1) / SB, Lb, Gb);
     double d0r = 0, d0i = 0, d1r = 0, d1i = 0;
     if (live) {
         for (int grp = sw.first; grp < sw.end; grp += sw.step) {
@@ -401,6 +404,8 @@ __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::lin
             partials[((size_t)0 * Gb + Lb) * N + r] = s0;
             if (EPI != EPI_DOT_AUX) partials[((size_t)1 * Gb + Lb) * N + r] = s1;
         }
+        if (tile + 1 < tile1) __syncthreads();  // red[] is reused by the next tile
+    }
     }
 }
 

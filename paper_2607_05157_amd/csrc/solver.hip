@@ -147,6 +147,7 @@ Shape site_shape(const wdt_lattice_s &lat, int N, int prec) {
     }
     sh.bz = bz;
     sh.bt = lat.dims[3];
+    sh.serial = tu.serial > 0;
     return sh;
 }
 

@@ -315,12 +315,13 @@ def profile_read():
     return out
 
 
-def set_launch_shape(rhs_tile=0, sites_per_block=0, max_blocks=0, z_slab=0):
-    """Override the launch shape of the (site, rhs) kernels (0 = automatic)."""
+def set_launch_shape(rhs_tile=0, sites_per_block=0, max_blocks=0, z_slab=0, serial_tiles=-1):
+    """Override the launch shape of the (site, rhs) kernels (0, or -1 for
+    serial_tiles, = automatic)."""
     L = lib()
     L.wdt_set_launch_shape.restype = ctypes.c_int
-    L.wdt_set_launch_shape.argtypes = [ctypes.c_int32] * 4
-    check(L.wdt_set_launch_shape(rhs_tile, sites_per_block, max_blocks, z_slab),
+    L.wdt_set_launch_shape.argtypes = [ctypes.c_int32] * 5
+    check(L.wdt_set_launch_shape(rhs_tile, sites_per_block, max_blocks, z_slab, serial_tiles),
           "wdt_set_launch_shape")
 
 

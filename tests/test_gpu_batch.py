@@ -89,3 +89,25 @@ def test_batched_workload_shapes_small():
         W.solve(s["g"], s["m0"], s["b"], xr, s["N"], tol=1e-10)
         # both meet 1e-10; the solutions agree to the tolerance times cond(D)
         assert torch.max(torch.abs(x - xr)).item() < 1e-8 * torch.max(torch.abs(xr)).item()
+
+
+def test_batched_uneven_convergence_redeals_blocks():
+    """Systems that converge many iterations apart (a heavy mass next to light
+    ones), checked every iteration so the block budget is dealt again each
+    time one finishes; two solves in a row on the same batch."""
+    specs = [((4, 4, 4, 4), 0.3, 3.0, 8), ((4, 4, 2, 8), 0.5, 0.02, 24), ((2, 4, 4, 6), 0.4, 1.0, 16),
+             ((6, 4, 4, 4), 0.2, 0.05, 40)]
+    say("batched uneven convergence", len(specs))
+    sys = _systems(specs)
+    B = W.Batch([s["g"] for s in sys], [s["m0"] for s in sys], [s["N"] for s in sys])
+    for rep in range(2):
+        xs = [s["lat"].new_batch(s["N"]) for s in sys]
+        rc, st = B.solve([s["b"] for s in sys], xs, tol=1e-11, check_every=1)
+        assert rc == W.OK and all(t["converged"] for t in st)
+        its = [t["iterations"] for t in st]
+        assert its[0] < its[8] // 2  # the heavy system finishes far earlier
+        for s, x in zip(sys, xs):
+            D = dirac.dense_D(s["U"], s["m0"], s["dims"], -1)
+            ref = osolve.dense_solve(D, s["b"].cpu().numpy().reshape(-1, s["N"]))
+            got = x.cpu().numpy().reshape(-1, s["N"])
+            assert np.max(np.abs(got - ref)) < 1e-9 * np.max(np.abs(ref))

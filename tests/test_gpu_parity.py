@@ -314,3 +314,48 @@ def test_force_matches_oracle():
     refm = oforce.grad_m0([xs[:, :, k] for k in range(N)], [ys[:, :, k] for k in range(N)], gout)
     assert np.max(np.abs(gU.cpu().numpy() - refU)) < 1e-13 * np.max(np.abs(refU))
     assert abs(gm - refm) < 1e-12 * abs(refm)
+
+
+# ---------------------------------------------------------------------------
+# launch shapes: every tuner setting computes the same operator and solve
+
+SHAPES = [  # (rhs_tile, sites_per_block, max_blocks, z_slab, serial_tiles)
+    (8, 0, 0, 0, 1),       # tiles swept in turn, ragged last tile (N = 20)
+    (8, 0, 24, 1, 1),      # few blocks, thinnest slab
+    (16, 0, 8, 2, 0),      # tiles side by side
+    (6, 5, 40, 0, 1),      # odd tile and block shape
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_launch_shapes_operator_and_solve(c1, shape):
+    say("launch shape", shape)
+    dims = (4, 4, 4, 6)
+    N = 20
+    V = int(np.prod(dims))
+    U = gauge_field(dims, 0.4, seed=9)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    psi = rand_batch(V, N, 5)
+    ref = dirac.apply_D(U, 0.1, psi, dims, -1)
+    try:
+        W.set_launch_shape(*shape)
+        out = lat.new_batch(N)
+        W.apply_D(g, 0.1, to_dev(psi), out, N, W.FP64)
+        err = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(np.abs(ref))
+        assert err < 1e-14, err
+        # the fused dot epilogues of the solver run under the same shape
+        dims1, m0, U1, Dinv = c1
+        lat1 = W.Lattice(dims1, -1)
+        g1 = W.Gauge(lat1, U1)
+        b = lat1.new_batch(N)
+        W.sources(lat1, W.source_descs(list(range(N))), b)
+        for prec, tol, bar in ((W.FP64, 1e-12, 1e-10), (W.FP16, 1e-10, 1e-8)):
+            x = lat1.new_batch(N)
+            rc, st = W.solve(g1, m0, b, x, N, tol=tol, prec=prec)
+            assert all(s["converged"] for s in st)
+            X = Dinv @ b.cpu().numpy().reshape(-1, N)
+            xs = x.cpu().numpy().reshape(-1, N)
+            assert np.max(np.linalg.norm(xs - X, axis=0) / np.linalg.norm(X, axis=0)) < bar
+    finally:
+        W.set_launch_shape(0, 0, 0, 0, -1)
