@@ -266,18 +266,33 @@ typedef struct {
 } wdt_prof_entry;
 
 /*
- * Launch-shape overrides for the tuner (all kernels over (site, rhs)):
- * rhs_tile = right-hand sides per tile (the batch is swept tile by tile),
- * sites_per_block = sites a block handles per step, max_blocks = blocks per
- * tile, z_slab = thickness (a divisor of Lz) of the z-slabs of the order in
- * which sites are visited (t-neighbours are Lx*Ly*z_slab sites apart in that
- * order), serial_tiles = 1 to have each operator block sweep the RHS tiles
- * one after the other (0: tiles side by side in the grid).  0 (-1 for
- * serial_tiles) restores the automatic choice.  Process-wide; not
- * thread-safe.
+ * Launch-shape overrides for the tuner (all kernels over (site, rhs)).
+ * Zero in a field keeps the automatic choice, except where -1 is stated.
+ *  rhs_tile         right-hand sides per tile (the batch is swept tile by tile)
+ *  sites_per_block  sites (or columns, when marching) a block handles per step
+ *  max_blocks       blocks per tile
+ *  z_slab           thickness (a divisor of Lz) of the z-slabs of the site
+ *                   order (t-neighbours are Lx*Ly*z_slab sites apart in it)
+ *  serial_tiles     1: each operator block sweeps the RHS tiles one after
+ *                   the other; 0: tiles side by side in the grid; -1 automatic
+ *  t_chunk          > 0: the operator marches along t through columns in
+ *                   chunks of t_chunk slices (a divisor of Lt); 0: site
+ *                   sweep; -1 automatic
+ *  brick            site sweep in brick order: bricks of brick[0] x brick[1]
+ *                   x brick[2] columns (divisors of Lx, Ly, Lz) visited one
+ *                   after the other, each through all of t; {0,0,0} automatic,
+ *                   {-1,-1,-1} off
+ *  wave_per_site    1: the operator gives each site one wavefront (its 64
+ *                   lanes are the RHS; batches of 48 or 64); 0 off; -1 automatic
+ * Invalid combinations for a lattice fall back to the automatic choice.
+ * Process-wide; not thread-safe.
  */
-int wdt_set_launch_shape(int32_t rhs_tile, int32_t sites_per_block, int32_t max_blocks,
-                         int32_t z_slab, int32_t serial_tiles);
+typedef struct {
+    int32_t rhs_tile, sites_per_block, max_blocks, z_slab, serial_tiles, t_chunk;
+    int32_t brick[3];
+    int32_t wave_per_site;
+} wdt_launch_shape;
+int wdt_set_launch_shape(const wdt_launch_shape *shape);
 
 int wdt_profile_enable(int on);
 /* Fills up to max entries; *n receives the number of kernel classes. */

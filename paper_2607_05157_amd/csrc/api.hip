@@ -34,7 +34,7 @@ size_t site_bytes(int prec) {
     return prec == WDT_FP64 ? 192 : prec == WDT_FP32 ? 96 : 52;
 }
 size_t link_bytes(int prec) {
-    return prec == WDT_FP64 ? 144 : 72;  // FP16 storage uses FP32 links
+    return prec == WDT_FP64 ? 144 : 72;  // FP32 links; FP16: two packed halves per element
 }
 
 // ---------------------------------------------------------------------------
@@ -103,12 +103,16 @@ ProfScope::~ProfScope() {
     if (stop) (void)hipEventRecord(stop, stream);
 }
 
-// Converts FP64 links to the FP32 copy (used by the FP32 and FP16 operators).
-__global__ void k_links_lower(const double2 *__restrict__ U, float2 *__restrict__ U32, int64_t n) {
+// Converts FP64 links to the FP32 copy (FP32 operator) and to the paired
+// half form of the FP16 operator: element u -> (ur, -ui), (ui, ur).
+__global__ void k_links_lower(const double2 *__restrict__ U, float2 *__restrict__ U32,
+                              __half2 *__restrict__ U16, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double2 u = U[i];
         U32[i] = make_float2((float)u.x, (float)u.y);
+        U16[2 * i] = __floats2half2_rn((float)u.x, -(float)u.y);
+        U16[2 * i + 1] = __floats2half2_rn((float)u.y, (float)u.x);
     }
 }
 
@@ -226,22 +230,25 @@ int wdt_gauge_create(wdt_lattice lat, const double *host_links, wdt_gauge *out) 
     const int64_t n = lat->V * 4 * 9;
     hipError_t e1 = hipMalloc(&g->U64, n * sizeof(double2));
     hipError_t e2 = hipMalloc(&g->U32, n * sizeof(float2));
-    if (e1 != hipSuccess || e2 != hipSuccess) {
+    hipError_t e3 = hipMalloc(&g->U16, 2 * n * sizeof(__half2));
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
         (void)hipGetLastError();
         if (g->U64) (void)hipFree(g->U64);
         if (g->U32) (void)hipFree(g->U32);
+        if (g->U16) (void)hipFree(g->U16);
         delete g;
         return set_error(WDT_ENOMEM, "wdt_gauge_create: device allocation failed");
     }
     hipError_t e = hipMemcpy(g->U64, host_links, n * sizeof(double2), hipMemcpyHostToDevice);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_links_lower, dim3(1024), dim3(256), 0, 0, g->U64, g->U32, n);
+        hipLaunchKernelGGL(k_links_lower, dim3(1024), dim3(256), 0, 0, g->U64, g->U32, g->U16, n);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         (void)hipFree(g->U64);
         (void)hipFree(g->U32);
+        (void)hipFree(g->U16);
         delete g;
         return set_error(WDT_EHIP, "wdt_gauge_create: %s", hipGetErrorString(e));
     }
@@ -253,6 +260,7 @@ int wdt_gauge_destroy(wdt_gauge g) {
     if (!g) return WDT_OK;
     (void)hipFree(g->U64);
     (void)hipFree(g->U32);
+    (void)hipFree(g->U16);
     if (g->ws.ptr) (void)hipFree(g->ws.ptr);
     delete g;
     return WDT_OK;
@@ -264,20 +272,33 @@ int wdt_gauge_get(wdt_gauge g, double *host_links) {
     return WDT_OK;
 }
 
-int wdt_set_launch_shape(int32_t rhs_tile, int32_t sites_per_block, int32_t max_blocks,
-                         int32_t z_slab, int32_t serial_tiles) {
-    WDT_CHECK(rhs_tile >= 0 && rhs_tile <= 256, "wdt_set_launch_shape: rhs_tile must be 0..256");
-    WDT_CHECK(sites_per_block >= 0 && sites_per_block <= 256,
+int wdt_set_launch_shape(const wdt_launch_shape *sh) {
+    WDT_CHECK(sh != nullptr, "wdt_set_launch_shape: null shape");
+    WDT_CHECK(sh->rhs_tile >= 0 && sh->rhs_tile <= 256, "wdt_set_launch_shape: rhs_tile must be 0..256");
+    WDT_CHECK(sh->sites_per_block >= 0 && sh->sites_per_block <= 256,
               "wdt_set_launch_shape: sites_per_block must be 0..256");
-    WDT_CHECK(max_blocks >= 0, "wdt_set_launch_shape: max_blocks must be >= 0");
-    tuning().nt = rhs_tile;
-    tuning().sb = sites_per_block;
-    WDT_CHECK(z_slab >= 0, "wdt_set_launch_shape: z_slab must be >= 0");
-    WDT_CHECK(serial_tiles >= -1 && serial_tiles <= 1,
+    WDT_CHECK(sh->max_blocks >= 0, "wdt_set_launch_shape: max_blocks must be >= 0");
+    WDT_CHECK(sh->z_slab >= 0, "wdt_set_launch_shape: z_slab must be >= 0");
+    WDT_CHECK(sh->serial_tiles >= -1 && sh->serial_tiles <= 1,
               "wdt_set_launch_shape: serial_tiles must be -1, 0 or 1");
-    tuning().gmax = max_blocks;
-    tuning().bz = z_slab;
-    tuning().serial = serial_tiles;
+    WDT_CHECK(sh->t_chunk >= -1, "wdt_set_launch_shape: t_chunk must be >= -1");
+    const bool brick_off = sh->brick[0] == -1 && sh->brick[1] == -1 && sh->brick[2] == -1;
+    const bool brick_auto = sh->brick[0] == 0 && sh->brick[1] == 0 && sh->brick[2] == 0;
+    WDT_CHECK(brick_off || brick_auto ||
+                  (sh->brick[0] > 0 && sh->brick[1] > 0 && sh->brick[2] > 0 &&
+                   sh->brick[0] < 100 && sh->brick[1] < 100 && sh->brick[2] < 100),
+              "wdt_set_launch_shape: brick must be {0,0,0}, {-1,-1,-1} or three extents 1..99");
+    LaunchTuning &t = tuning();
+    t.nt = sh->rhs_tile;
+    t.sb = sh->sites_per_block;
+    t.gmax = sh->max_blocks;
+    t.bz = sh->z_slab;
+    t.serial = sh->serial_tiles;
+    t.tchunk = sh->t_chunk;
+    t.brick = brick_off ? -1 : brick_auto ? 0 : sh->brick[0] * 10000 + sh->brick[1] * 100 + sh->brick[2];
+    WDT_CHECK(sh->wave_per_site >= -1 && sh->wave_per_site <= 1,
+              "wdt_set_launch_shape: wave_per_site must be -1, 0 or 1");
+    t.wps = sh->wave_per_site;
     return WDT_OK;
 }
 

@@ -45,8 +45,10 @@ struct Geom {
     int V;
     int Lxyz;
     int bc_t;
-    // Processing order of the sites (see site_of): tiles of Lx*Ly*bz*bt sites.
+    // Processing order of the sites (see site_of): tiles of Lx*Ly*bz*bt sites,
+    // or, when bx > 0, bricks of bx*by*bz columns marched through all of t.
     int bz, bt;
+    int bx, by;
 };
 
 // Site index of processing position p.  The lattice is cut into tiles of
@@ -55,6 +57,23 @@ struct Geom {
 // directions (a t-neighbour is Lx*Ly*bz positions away instead of Lx*Ly*Lz),
 // which lets an XCD's L2 serve the neighbour re-reads of the operator.
 __device__ __forceinline__ int site_of(const Geom &g, int p) {
+    if (g.bx > 0) {
+        // brick order: brick by brick, each brick one time slice after the
+        // other, x fastest inside a slice of the brick
+        const int bvol = g.bx * g.by * g.bz;
+        const int per_brick = bvol * g.L[3];
+        const int brick = p / per_brick;
+        int q = p - brick * per_brick;
+        const int t = q / bvol;
+        q -= t * bvol;
+        const int nbx = g.L[0] / g.bx, nby = g.L[1] / g.by;
+        const int bxi = brick % nbx, byi = (brick / nbx) % nby, bzi = brick / (nbx * nby);
+        const int x = bxi * g.bx + q % g.bx;
+        q /= g.bx;
+        const int y = byi * g.by + q % g.by;
+        const int z = bzi * g.bz + q / g.by;
+        return x + g.L[0] * (y + g.L[1] * (z + g.L[2] * t));
+    }
     if (g.bz == g.L[2] && g.bt == g.L[3]) return p;
     const int tvol = g.Lxyz / g.L[2] * g.bz * g.bt;
     const int tile = p / tvol;
@@ -114,9 +133,8 @@ __device__ __forceinline__ SiteNbr neighbours(const Geom &g, int s) {
 // Spinor batch formats: [V][12][N] with the RHS index innermost.
 //  F64: double2; F32: float2; F16: __half2 plus a float scale per (site, rhs)
 //  stored after the V*12*N half2 values.
-//  `link` is the element type of the links the operator reads: FP16 storage
-//  keeps FP32 links (they are a small share of the bytes, and converting a
-//  link in every lane would cost more ALU time than it saves in traffic).
+//  `link` is the element type of the links the operator reads; the FP16
+//  operator reads half links in a paired form made for half dot products.
 struct F64 {
     using real = double;
     using elem = double2;
@@ -132,7 +150,7 @@ struct F32 {
 struct F16 {
     using real = float;
     using elem = __half2;
-    using link = float2;
+    using link = __half2;  // two per link element: (ur, -ui), (ui, ur)
     static constexpr bool scaled = true;
 };
 
@@ -178,6 +196,33 @@ __device__ __forceinline__ typename S::real load_site_raw(const SpinorPtr<S> &sp
             v[k] = {e.x, e.y};
         }
         return typename S::real(1);
+    }
+}
+
+// The 12 stored elements of (site, r) as they are in memory (no conversion);
+// returns the scale (1 for unscaled formats).
+template <class S, int NC = 0>
+__device__ __forceinline__ typename S::real load_site_elems(const SpinorPtr<S> &sp, int site, int r,
+                                                            typename S::elem (&e)[12]) {
+    const int N = batch_n<S, NC>(sp);
+    const typename S::elem *q = sp.p + (size_t)site * 12 * N + r;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) e[k] = q[k * N];
+    if constexpr (S::scaled) return sp.scale[(size_t)site * N + r];
+    else return typename S::real(1);
+}
+
+template <class S>
+__device__ __forceinline__ void elems_to_cplx(const typename S::elem (&e)[12],
+                                              cplx<typename S::real> (&v)[12]) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        if constexpr (S::scaled) {
+            const float2 f = __half22float2(e[k]);
+            v[k] = {f.x, f.y};
+        } else {
+            v[k] = {e[k].x, e[k].y};
+        }
     }
 }
 

@@ -29,7 +29,7 @@
 
 namespace wdt {
 
-template <class S, int NC, bool DAG, int EPI>
+template <class S, int NC, bool DAG, int EPI, bool WPS = false>
 __global__ __launch_bounds__(256) void k_dslash(Geom g, const typename S::link *__restrict__ U,
                                                 typename S::real diag, SpinorPtr<S> in,
                                                 SpinorPtr<S> out, SpinorPtr<S> aux, int N, int NT,
@@ -37,8 +37,18 @@ __global__ __launch_bounds__(256) void k_dslash(Geom g, const typename S::link *
                                                 int serial_tiles) {
     const int t0 = serial_tiles > 0 ? 0 : (int)blockIdx.y;
     const int t1 = serial_tiles > 0 ? serial_tiles : t0 + 1;
-    dslash_body<S, NC, DAG, EPI>(g, U, diag, in, out, aux, N, NT, SB, partials, t0, t1,
-                                 xcd_block(blockIdx.x, gridDim.x), gridDim.x);
+    dslash_body<S, NC, DAG, EPI, WPS>(g, U, diag, in, out, aux, N, NT, SB, partials, t0, t1,
+                                      xcd_block(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+template <class S, int NC, bool DAG, int EPI>
+__global__ __launch_bounds__(256) void k_dslash_march(Geom g, const typename S::link *__restrict__ U,
+                                                      typename S::real diag, SpinorPtr<S> in,
+                                                      SpinorPtr<S> out, SpinorPtr<S> aux, int N,
+                                                      int NT, int CB, int TC, int4 B,
+                                                      double2 *__restrict__ partials) {
+    dslash_march_body<S, NC, DAG, EPI>(g, U, diag, in, out, aux, N, NT, CB, TC, B, partials,
+                                       blockIdx.y, xcd_block(blockIdx.x, gridDim.x), gridDim.x);
 }
 
 // Batch sizes with a compiled-in constant (other sizes use the runtime path).
@@ -52,9 +62,20 @@ template <class S, int NC, bool DAG, int EPI>
 static void launch_k(dim3 grid, int threads, hipStream_t stream, const Geom &g,
                      const typename S::link *U, typename S::real diag, SpinorPtr<S> pin_,
                      SpinorPtr<S> pout, SpinorPtr<S> paux, int N, int NT, int SB, double2 *part,
-                     int serial_tiles) {
-    hipLaunchKernelGGL((k_dslash<S, NC, DAG, EPI>), grid, dim3(threads), 0, stream, g, U, diag,
-                       pin_, pout, paux, N, NT, SB, part, serial_tiles);
+                     int serial_tiles, int tc, int4 brick, bool wps) {
+    if constexpr (NC == 48 || NC == 64) {
+        if (wps && tc == 0) {
+            hipLaunchKernelGGL((k_dslash<S, NC, DAG, EPI, true>), grid, dim3(threads), 0, stream,
+                               g, U, diag, pin_, pout, paux, N, NT, SB, part, serial_tiles);
+            return;
+        }
+    }
+    if (tc > 0)
+        hipLaunchKernelGGL((k_dslash_march<S, NC, DAG, EPI>), grid, dim3(threads), 0, stream, g,
+                           U, diag, pin_, pout, paux, N, NT, SB, tc, brick, part);
+    else
+        hipLaunchKernelGGL((k_dslash<S, NC, DAG, EPI>), grid, dim3(threads), 0, stream, g, U,
+                           diag, pin_, pout, paux, N, NT, SB, part, serial_tiles);
 }
 
 template <class S, bool DAG, int EPI>
@@ -63,8 +84,12 @@ static int launch_t(const wdt_gauge_s *gf, double m0, const void *in, void *out,
                     const typename S::link *U) {
     const Geom g = shaped_geom(gf->lat, sh);
     const int V = g.V;
-    const dim3 grid(sh.G, sh.serial ? 1 : sh.tiles);
-    const int serial_tiles = sh.serial ? sh.tiles : 0;
+    // one site per wavefront: 64 lanes per site, four sites per block
+    const bool wps = sh.wps && sh.tc == 0 && (nc_of(N) == 48 || nc_of(N) == 64);
+    const int NT = wps ? 64 : sh.NT, SB = wps ? 4 : sh.SB, threads = wps ? 256 : sh.threads;
+    const int tiles = (N + NT - 1) / NT;
+    const dim3 grid(sh.G, (sh.serial && sh.tc == 0) ? 1 : tiles);
+    const int serial_tiles = sh.serial ? tiles : 0;
     SpinorPtr<S> pin_ = make_spinor<S>(const_cast<void *>(in), V, N);
     SpinorPtr<S> pout = make_spinor<S>(out, V, N);
     SpinorPtr<S> paux = make_spinor<S>(const_cast<void *>(aux), V, N);
@@ -77,20 +102,20 @@ static int launch_t(const wdt_gauge_s *gf, double m0, const void *in, void *out,
     const typename S::real diag = (typename S::real)(4.0 + m0);
     switch (nc_of(N)) {
         case 16:
-            launch_k<S, 16, DAG, EPI>(grid, sh.threads, stream, g, U, diag, pin_, pout, paux, N,
-                                     sh.NT, sh.SB, partials, serial_tiles);
+            launch_k<S, 16, DAG, EPI>(grid, threads, stream, g, U, diag, pin_, pout, paux, N,
+                                     NT, SB, partials, serial_tiles, sh.tc, sh.brick, sh.wps);
             break;
         case 48:
-            launch_k<S, 48, DAG, EPI>(grid, sh.threads, stream, g, U, diag, pin_, pout, paux, N,
-                                     sh.NT, sh.SB, partials, serial_tiles);
+            launch_k<S, 48, DAG, EPI>(grid, threads, stream, g, U, diag, pin_, pout, paux, N,
+                                     NT, SB, partials, serial_tiles, sh.tc, sh.brick, sh.wps);
             break;
         case 64:
-            launch_k<S, 64, DAG, EPI>(grid, sh.threads, stream, g, U, diag, pin_, pout, paux, N,
-                                     sh.NT, sh.SB, partials, serial_tiles);
+            launch_k<S, 64, DAG, EPI>(grid, threads, stream, g, U, diag, pin_, pout, paux, N,
+                                     NT, SB, partials, serial_tiles, sh.tc, sh.brick, sh.wps);
             break;
         default:
-            launch_k<S, 0, DAG, EPI>(grid, sh.threads, stream, g, U, diag, pin_, pout, paux, N,
-                                    sh.NT, sh.SB, partials, serial_tiles);
+            launch_k<S, 0, DAG, EPI>(grid, threads, stream, g, U, diag, pin_, pout, paux, N,
+                                    NT, SB, partials, serial_tiles, sh.tc, sh.brick, sh.wps);
             break;
     }
     WDT_HIP(hipGetLastError());
@@ -125,7 +150,7 @@ int launch_dslash(const wdt_gauge_s *g, double m0, int prec, int dagger, int epi
         case WDT_FP32:
             return launch_p<F32>(g, m0, dagger, epi, in, out, aux, N, partials, sh, stream, g->U32);
         case WDT_FP16:
-            return launch_p<F16>(g, m0, dagger, epi, in, out, aux, N, partials, sh, stream, g->U32);
+            return launch_p<F16>(g, m0, dagger, epi, in, out, aux, N, partials, sh, stream, g->U16);
         default:
             return set_error(WDT_EINVAL, "bad precision %d", prec);
     }
@@ -134,37 +159,43 @@ int launch_dslash(const wdt_gauge_s *g, double m0, int prec, int dagger, int epi
 // Resident blocks per CU of the operator kernel (the solve-time variant),
 // used to size grids so that every block of a sweep is on the GPU at once.
 template <class S, int NC>
-static int occ_t(int threads) {
+static int occ_t(int threads, int mode) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_dslash<S, NC, false, EPI_DOT_AUX>,
-                                                     threads, 0) != hipSuccess) {
+    hipError_t e;
+    if (mode == 1)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, k_dslash_march<S, NC, false, EPI_DOT_AUX>, threads, 0);
+    else if (mode == 2 && (NC == 48 || NC == 64))
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, k_dslash<S, NC, false, EPI_DOT_AUX, (NC == 48 || NC == 64)>, threads, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, k_dslash<S, NC, false, EPI_DOT_AUX>, threads, 0);
+    if (e != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
     return nb;
 }
 
-int op_blocks_per_cu(int prec, int N, int threads) {
+template <class S>
+static int occ_p(int N, int threads, int mode) {
+    switch (nc_of(N)) {
+        case 16: return occ_t<S, 16>(threads, mode);
+        case 48: return occ_t<S, 48>(threads, mode);
+        case 64: return occ_t<S, 64>(threads, mode);
+        default: return occ_t<S, 0>(threads, mode);
+    }
+}
+
+int op_blocks_per_cu(int prec, int N, int threads, int mode) {
     static std::map<long, int> cache;
-    const long key = ((long)prec << 40) | ((long)N << 16) | threads;
+    const long key = ((long)prec << 42) | ((long)mode << 40) | ((long)N << 16) | threads;
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
-    int nb = 0;
-    const int nc = nc_of(N);
-    switch (prec) {
-        case WDT_FP64:
-            nb = nc == 16 ? occ_t<F64, 16>(threads) : nc == 48 ? occ_t<F64, 48>(threads)
-               : nc == 64 ? occ_t<F64, 64>(threads) : occ_t<F64, 0>(threads);
-            break;
-        case WDT_FP32:
-            nb = nc == 16 ? occ_t<F32, 16>(threads) : nc == 48 ? occ_t<F32, 48>(threads)
-               : nc == 64 ? occ_t<F32, 64>(threads) : occ_t<F32, 0>(threads);
-            break;
-        default:
-            nb = nc == 16 ? occ_t<F16, 16>(threads) : nc == 48 ? occ_t<F16, 48>(threads)
-               : nc == 64 ? occ_t<F16, 64>(threads) : occ_t<F16, 0>(threads);
-            break;
-    }
+    const int nb = prec == WDT_FP64   ? occ_p<F64>(N, threads, mode)
+                   : prec == WDT_FP32 ? occ_p<F32>(N, threads, mode)
+                                      : occ_p<F16>(N, threads, mode);
     cache[key] = nb;
     return nb;
 }

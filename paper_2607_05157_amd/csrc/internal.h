@@ -28,6 +28,7 @@ struct wdt_lattice_s {
         g.bc_t = bc_t;
         g.bz = dims[2];
         g.bt = dims[3];
+        g.bx = g.by = 0;
         return g;
     }
 };
@@ -43,6 +44,9 @@ struct wdt_gauge_s {
     wdt_lattice_s lat;
     double2 *U64 = nullptr;
     float2 *U32 = nullptr;
+    // FP16 operator links: per element u = (ur, ui) the pair (ur, -ui), (ui, ur)
+    // of packed halves, so that both parts of u h are single half dot products
+    __half2 *U16 = nullptr;
     Workspace ws;
 };
 
@@ -98,10 +102,16 @@ struct Shape {
     int Gv;       // blocks per tile of the vector (BLAS-1) kernels
     int bz, bt;   // processing-order tile (see site_of)
     bool serial;  // operator blocks sweep the RHS tiles one after the other
+    int tc;       // > 0: the operator marches along t in chunks of tc slices (SB columns
+                  // per block, G blocks over the units); 0: it sweeps sites
+    int4 brick;   // march: column bricks (x, y, z extents; x a multiple of SB)
+    int4 sweep_brick;  // sweep in brick order (x, y, z extents) when x > 0
+    bool wps;     // operator: one site per wavefront (64 RHS lanes, 4 sites per block)
 };
 Shape site_shape(const wdt_lattice_s &lat, int N, int prec);
 // Resident blocks per CU of the operator kernel for (prec, N, block size).
-int op_blocks_per_cu(int prec, int N, int threads);
+// mode: 0 site sweep, 1 t-march, 2 site sweep with one site per wavefront
+int op_blocks_per_cu(int prec, int N, int threads, int mode);
 // The lattice geometry with the processing order of a shape.
 wdt::Geom shaped_geom(const wdt_lattice_s &lat, const Shape &sh);
 
@@ -109,6 +119,9 @@ wdt::Geom shaped_geom(const wdt_lattice_s &lat, const Shape &sh);
 struct LaunchTuning {
     int nt = 0, sb = 0, gmax = 0, bz = 0;
     int serial = -1;  // RHS tiles one after the other in each block: 1 on, 0 off, -1 automatic
+    int tchunk = -1;  // operator marches along t in chunks of this many slices: 0 off, -1 automatic
+    int brick = 0;    // sweep order bricks: 0 automatic, -1 off, else x*10000 + y*100 + z
+    int wps = -1;     // operator one site per wavefront: 1 on, 0 off, -1 automatic
 };
 LaunchTuning &tuning();
 

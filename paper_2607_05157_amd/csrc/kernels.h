@@ -265,6 +265,25 @@ __device__ __forceinline__ void pin(cplx<T> (&a)[12]) {
     for (int k = 0; k < 12; ++k) asm volatile("" : "+v"(a[k].re), "+v"(a[k].im));
 }
 
+// Keeps loaded elements in registers from this point on: the inputs are
+// read-only, so the compiler may otherwise load a carried value again at
+// the end of a loop body, and the next iteration then waits for that load
+// behind the stores issued after it.
+template <class E>
+__device__ __forceinline__ void pin_elems(E (&e)[12]) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        if constexpr (sizeof(E) == 4) {
+            unsigned u;
+            __builtin_memcpy(&u, &e[k], 4);
+            asm volatile("" : "+v"(u));
+            __builtin_memcpy(&e[k], &u, 4);
+        } else {
+            asm volatile("" : "+v"(e[k].x), "+v"(e[k].y));
+        }
+    }
+}
+
 // Schedule per precision: one direction (two spinors, two links) in flight.
 template <class S> struct OpPin { static constexpr int value = 1; };
 
@@ -274,55 +293,180 @@ template <class S> struct OpPin { static constexpr int value = 1; };
 #define WDT_OP_STREAM_STORES 1
 #endif
 
+// ---------------------------------------------------------------------------
+// FP16 operator arithmetic.  The half spinor is formed in packed half
+// precision (one packed add per colour component, the unit factor folded into
+// the add's operand modifiers), and each part of a link-times-half-spinor
+// product is a chain of three two-term half dot products accumulated in FP32
+// (v_dot2), with the link element stored as the pairs (ur, -ui) and (ui, ur).
+// A hop then costs 36 dot products instead of 72 FP32 multiply-adds and the
+// 24 conversions of the neighbour spinor.
+typedef _Float16 hv2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ hv2 as_hv2(__half2 a) {
+    hv2 r;
+    __builtin_memcpy(&r, &a, 4);
+    return r;
+}
+
+// i^K z for z = (re, im)
+template <int K>
+__device__ __forceinline__ hv2 hunit(hv2 z) {
+    if constexpr ((K & 3) == 0) return z;
+    else if constexpr ((K & 3) == 1) return hv2{-z.y, z.x};
+    else if constexpr ((K & 3) == 2) return hv2{-z.x, -z.y};
+    else return hv2{z.y, -z.x};
+}
+
+// rows 0, 1 of (1 + SGN gamma_mu) psi (the same tables as project())
+template <int MU, int SGN>
+__device__ __forceinline__ void hproject(const __half2 (&psi)[12], hv2 (&h)[6]) {
+    using P = Proj<MU>;
+    constexpr int sh = (SGN < 0) ? 0 : 2;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        h[c] = as_hv2(psi[c]) + hunit<P::a0 + sh>(as_hv2(psi[3 * P::p0 + c]));
+        h[3 + c] = as_hv2(psi[3 + c]) + hunit<P::a1 + sh>(as_hv2(psi[3 * P::p1 + c]));
+    }
+}
+
+// w = U h (ADJ = false) or U^dag h (ADJ = true); u in the paired form
+template <bool ADJ>
+__device__ __forceinline__ void hsu3(const __half2 (&u)[18], const hv2 (&h)[6],
+                                     cplx<float> (&w)[6]) {
+    hv2 hs[6];
+    if constexpr (ADJ) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) hs[k] = hv2{h[k].y, h[k].x};
+    }
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                if constexpr (!ADJ) {
+                    // (ur, -ui).(hr, hi) and (ui, ur).(hr, hi)
+                    re = __builtin_amdgcn_fdot2(as_hv2(u[2 * (3 * a + b)]), h[3 * hh + b], re, false);
+                    im = __builtin_amdgcn_fdot2(as_hv2(u[2 * (3 * a + b) + 1]), h[3 * hh + b], im, false);
+                } else {
+                    // conj(u_ba) h_b: (ui, ur).(hi, hr) and (ur, -ui).(hi, hr)
+                    re = __builtin_amdgcn_fdot2(as_hv2(u[2 * (3 * b + a) + 1]), hs[3 * hh + b], re, false);
+                    im = __builtin_amdgcn_fdot2(as_hv2(u[2 * (3 * b + a)]), hs[3 * hh + b], im, false);
+                }
+            }
+            w[3 * hh + a] = {re, im};
+        }
+}
+
+// acc += s * (full spinor of (1 + SGN gamma_mu) reconstructed from w), the
+// scale folded into the multiply-adds
+template <int MU, int SGN>
+__device__ __forceinline__ void reconstruct_add_scaled(cplx<float> (&acc)[12], const cplx<float> (&w)[6],
+                                                       float s) {
+    using P = Proj<MU>;
+    constexpr int sh = (SGN < 0) ? 0 : 2;
+    auto fma_s = [s](cplx<float> &a, cplx<float> z) {
+        a.re = fmaf(s, z.re, a.re);
+        a.im = fmaf(s, z.im, a.im);
+    };
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        fma_s(acc[c], w[c]);
+        fma_s(acc[3 + c], w[3 + c]);
+        fma_s(acc[6 + c], cunit<P::b2 + sh>(w[3 * P::q2 + c]));
+        fma_s(acc[9 + c], cunit<P::b3 + sh>(w[3 * P::q3 + c]));
+    }
+}
+
+// w = scale * U_mu(link_site) P psi (ADJ = false) or scale * U_mu(link_site)^dag
+// P psi (ADJ = true), P = rows 0, 1 of (1 + SGN gamma_mu); psi given as its
+// stored elements.
+template <class S, int MU, int SGN, bool ADJ>
+__device__ __forceinline__ void hop_w(const typename S::link *__restrict__ U, int link_site,
+                                      const typename S::elem (&e)[12], typename S::real scale,
+                                      cplx<typename S::real> (&w)[6]) {
+    using R = typename S::real;
+    if constexpr (S::scaled) {
+        __half2 u[18];
+        const __half2 *q = U + ((size_t)link_site * 4 + MU) * 18;
+#pragma unroll
+        for (int k = 0; k < 18; ++k) u[k] = q[k];
+        hv2 h[6];
+        hproject<MU, SGN>(e, h);
+        hsu3<ADJ>(u, h, w);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) w[k] = {w[k].re * scale, w[k].im * scale};
+    } else {
+        cplx<R> p[12], u[9], h[6];
+        elems_to_cplx<S>(e, p);
+        load_link<S, R>(U, link_site, MU, u);
+        project<MU, SGN>(p, h);
+        if (MU == 3) {  // the boundary sign rides on the scale
+#pragma unroll
+            for (int k = 0; k < 6; ++k) h[k] = {h[k].re * scale, h[k].im * scale};
+        }
+        if constexpr (ADJ) su3_adj_mul(u, h, w);
+        else su3_mul(u, h, w);
+    }
+}
+
+// acc += the reconstructed hop of hop_w (FP16: the scale folded into the adds)
+template <class S, int MU, int SGN, bool ADJ>
+__device__ __forceinline__ void hop_acc(const typename S::link *__restrict__ U, int link_site,
+                                        const typename S::elem (&e)[12], typename S::real scale,
+                                        cplx<typename S::real> (&acc)[12]) {
+    if constexpr (S::scaled) {
+        __half2 u[18];
+        const __half2 *q = U + ((size_t)link_site * 4 + MU) * 18;
+#pragma unroll
+        for (int k = 0; k < 18; ++k) u[k] = q[k];
+        hv2 h[6];
+        hproject<MU, SGN>(e, h);
+        cplx<float> w[6];
+        hsu3<ADJ>(u, h, w);
+        reconstruct_add_scaled<MU, SGN>(acc, w, scale);
+    } else {
+        cplx<typename S::real> w[6];
+        hop_w<S, MU, SGN, ADJ>(U, link_site, e, scale, w);
+        reconstruct_add<MU, SGN>(acc, w);
+    }
+}
+
 template <int MU, bool DAG, int PIN, int NC, class S>
 __device__ __forceinline__ void hop_pair(const Geom &g, const typename S::link *__restrict__ U,
                                          const SpinorPtr<S> &in, int s, const SiteNbr &nb, int r,
                                          cplx<typename S::real> (&acc)[12]) {
     using R = typename S::real;
+    using E = typename S::elem;
     constexpr int SF = DAG ? +1 : -1;  // forward projector (1 + SF gamma_mu)
     const int b = nb.bwd[MU];
-    cplx<R> pf[12], pb[12], uf[9], ub[9];
-    R sf = load_site_raw<S, NC>(in, nb.fwd[MU], r, pf);
-    load_link<S, R>(U, s, MU, uf);
+    E pf[12], pb[12];
+    R sf = load_site_elems<S, NC>(in, nb.fwd[MU], r, pf);
     R sb = R(1);
-    if constexpr (PIN != 2) {
-        sb = load_site_raw<S, NC>(in, b, r, pb);
-        load_link<S, R>(U, b, MU, ub);
-    }
+    if constexpr (PIN != 2) sb = load_site_elems<S, NC>(in, b, r, pb);
     {
-        // the FP16 scale and the time-boundary sign act on the half spinor
+        // the FP16 scale and the time-boundary sign act on the hop
         if (MU == 3 && nb.fwd_wrap_t && g.bc_t < 0) sf = -sf;
-        cplx<R> h[6];
-        project<MU, SF>(pf, h);
-        if constexpr (S::scaled || MU == 3) {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) h[k] = {h[k].re * sf, h[k].im * sf};
-        }
-        cplx<R> w[6];
-        su3_mul(uf, h, w);
-        reconstruct_add<MU, SF>(acc, w);
+        hop_acc<S, MU, SF, false>(U, s, pf, sf, acc);
     }
     if constexpr (PIN == 2) {
         pin(acc);
-        sb = load_site_raw<S, NC>(in, b, r, pb);
-        load_link<S, R>(U, b, MU, ub);
+        sb = load_site_elems<S, NC>(in, b, r, pb);
     }
     {
         if (MU == 3 && nb.bwd_wrap_t && g.bc_t < 0) sb = -sb;
-        cplx<R> h[6];
-        project<MU, -SF>(pb, h);
-        if constexpr (S::scaled || MU == 3) {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) h[k] = {h[k].re * sb, h[k].im * sb};
-        }
-        cplx<R> w[6];
-        su3_adj_mul(ub, h, w);
-        reconstruct_add<MU, -SF>(acc, w);
+        hop_acc<S, MU, -SF, true>(U, b, pb, sb, acc);
     }
     if constexpr (PIN != 0) pin(acc);
 }
 
-template <class S, int NC, bool DAG, int EPI>
+// WPS (one site per wavefront): NT = 64, the lanes are the RHS of one site,
+// so the site, its neighbours and the link addresses are wave-uniform; the
+// links then come through the scalar cache into SGPRs instead of occupying
+// the vector memory pipeline with 64 copies of the same address.
+template <class S, int NC, bool DAG, int EPI, bool WPS = false>
 __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::link *__restrict__ U,
                                             typename S::real diag, SpinorPtr<S> in,
                                             SpinorPtr<S> out, SpinorPtr<S> aux, int N, int NT,
@@ -332,8 +476,8 @@ __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::lin
     constexpr int PIN = OpPin<S>::value;
     __shared__ double2 red[2][256];
     const int tid = threadIdx.x;
-    const int rl = tid % NT;
-    const int ry = tid / NT;
+    const int rl = WPS ? (tid & 63) : tid % NT;
+    const int ry = WPS ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid / NT;
     const Sweep sw = sweep((g.V + SB - 1) / SB, Lb, Gb);
     // RHS tiles [tile0, tile1) one after the other: the XCD's L2 then holds
     // one tile's worth of each site instead of the whole batch
@@ -407,6 +551,191 @@ __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::lin
         if (tile + 1 < tile1) __syncthreads();  // red[] is reused by the next tile
     }
     }
+}
+
+// Per-RHS dot partials of the operator epilogues, reduced over the block and
+// written to partials[(d * Gb + Lb) * N + r] (d = 0, 1).
+template <int EPI>
+__device__ __forceinline__ void epi_reduce(double2 (&red)[2][256], int tid, int rl, int ry, int r,
+                                           int N, int NT, int SB, double d0r, double d0i,
+                                           double d1r, double d1i, double2 *__restrict__ partials,
+                                           int Lb, int Gb) {
+    red[0][tid] = make_double2(d0r, d0i);
+    red[1][tid] = make_double2(d1r, d1i);
+    __syncthreads();
+    if (ry == 0 && r < N) {
+        double2 s0 = red[0][rl], s1 = red[1][rl];
+        for (int y = 1; y < SB; ++y) {
+            const double2 a0 = red[0][y * NT + rl], a1 = red[1][y * NT + rl];
+            s0.x += a0.x;
+            s0.y += a0.y;
+            s1.x += a1.x;
+            s1.y += a1.y;
+        }
+        partials[((size_t)0 * Gb + Lb) * N + r] = s0;
+        if (EPI != EPI_DOT_AUX) partials[((size_t)1 * Gb + Lb) * N + r] = s1;
+    }
+}
+
+// Output of one site from the hop sum and the (scaled) own spinor, with the
+// epilogue's dot contributions; stores the result.
+template <class S, int NC, int EPI>
+__device__ __forceinline__ void finish_site(typename S::real diag, const cplx<typename S::real> (&c)[12],
+                                            const cplx<typename S::real> (&acc)[12], SpinorPtr<S> out,
+                                            SpinorPtr<S> aux, int s, int r, double &d0r,
+                                            double &d0i, double &d1r) {
+    using R = typename S::real;
+    cplx<R> o[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        o[k] = {diag * c[k].re - R(0.5) * acc[k].re, diag * c[k].im - R(0.5) * acc[k].im};
+    if constexpr (EPI == EPI_RESID) {
+        cplx<R> b[12];
+        load_site<S, NC>(aux, s, r, b);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            o[k] = csub(b[k], o[k]);
+            d0r += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
+            d1r += (double)b[k].re * b[k].re + (double)b[k].im * b[k].im;
+        }
+    } else if constexpr (EPI == EPI_DOT_AUX) {
+        cplx<R> a[12];
+        load_site<S, NC>(aux, s, r, a);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            d0r += (double)a[k].re * o[k].re + (double)a[k].im * o[k].im;
+            d0i += (double)a[k].re * o[k].im - (double)a[k].im * o[k].re;
+        }
+    } else if constexpr (EPI == EPI_DOT_TS) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            d0r += (double)o[k].re * c[k].re + (double)o[k].im * c[k].im;
+            d0i += (double)o[k].re * c[k].im - (double)o[k].im * c[k].re;
+            d1r += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
+        }
+    }
+    store_site<S, WDT_OP_STREAM_STORES != 0, NC>(out, s, r, o);
+}
+
+// The same operator with every thread marching along t through one spatial
+// column for one RHS.  The t-neighbours come from registers: the forward one
+// is the next step's own site, and the backward hop into (x, t+1) is formed
+// at step t from the own spinor and the link U_t(x, t) that the forward hop
+// loads anyway.  A site then costs six spatial neighbour reads and one new
+// spinor instead of nine reads, and seven links instead of eight; the
+// column's spatial neighbours are computed once per column.  The columns
+// are cut into bricks of B[0] x B[1] x B[2] (B[0] a multiple of CB); a work
+// unit is CB consecutive columns of one brick row over TC consecutive time
+// slices, numbered chunk-major, then brick, then within the brick.  Each XCD
+// takes a contiguous range of units and its resident blocks take consecutive
+// units, so what an XCD marches through at once is a whole brick: the six
+// spatial reads of a site find the slice its neighbours loaded one step
+// earlier in that XCD's L2, except across the brick's faces.
+template <class S, int NC, bool DAG, int EPI>
+__device__ __forceinline__ void dslash_march_body(const Geom &g, const typename S::link *__restrict__ U,
+                                                  typename S::real diag, SpinorPtr<S> in,
+                                                  SpinorPtr<S> out, SpinorPtr<S> aux, int N,
+                                                  int NT, int CB, int TC, int4 B,
+                                                  double2 *__restrict__ partials, int tile, int Lb,
+                                                  int Gb) {
+    using R = typename S::real;
+    using E = typename S::elem;
+    constexpr int PIN = OpPin<S>::value;
+    constexpr int SF = DAG ? +1 : -1;
+    __shared__ double2 red[2][256];
+    const int tid = threadIdx.x;
+    const int rl = tid % NT;
+    const int ry = tid / NT;
+    const int r = tile * NT + rl;
+    const bool live = (ry < CB) && (r < N);
+    const int L0 = g.L[0], L1 = g.L[1], L2 = g.L[2], Lt = g.L[3];
+    const int Lxyz = g.Lxyz;
+    const int gx = B.x / CB;                              // column groups per brick row
+    const int upb = gx * B.y * B.z;                       // units per brick and chunk
+    const int nbx = L0 / B.x, nby = L1 / B.y, nbz = L2 / B.z;
+    const int ncg = upb * nbx * nby * nbz;                // units per chunk
+    const Sweep sw = sweep(ncg * (Lt / TC), Lb, Gb);
+    double d0r = 0, d0i = 0, d1r = 0, d1i = 0;
+    if (live) {
+        for (int u = sw.first; u < sw.end; u += sw.step) {
+            const int chunk = u / ncg;
+            int c, x, y, z;
+            {
+                int q = u - chunk * ncg;
+                const int brick = q / upb;
+                q -= brick * upb;
+                const int bxi = brick % nbx, byi = (brick / nbx) % nby, bzi = brick / (nbx * nby);
+                x = bxi * B.x + (q % gx) * CB + ry;
+                q /= gx;
+                y = byi * B.y + q % B.y;
+                z = bzi * B.z + q / B.y;
+                c = x + L0 * (y + L1 * z);
+            }
+            int cf[3], cb[3];
+            {
+                const int sxy = L0 * L1;
+                cf[0] = (x == L0 - 1) ? c - (L0 - 1) : c + 1;
+                cb[0] = (x == 0) ? c + (L0 - 1) : c - 1;
+                cf[1] = (y == L1 - 1) ? c - (L1 - 1) * L0 : c + L0;
+                cb[1] = (y == 0) ? c + (L1 - 1) * L0 : c - L0;
+                cf[2] = (z == L2 - 1) ? c - (L2 - 1) * sxy : c + sxy;
+                cb[2] = (z == 0) ? c + (L2 - 1) * sxy : c - sxy;
+            }
+            const int t0 = chunk * TC;
+            E ec[12];
+            R sc = load_site_elems<S, NC>(in, c + Lxyz * t0, r, ec);
+            // backward t-hop into (c, t0)
+            cplx<R> wb[6];
+            {
+                const int sbk = c + Lxyz * (t0 == 0 ? Lt - 1 : t0 - 1);
+                E pb[12];
+                R sb = load_site_elems<S, NC>(in, sbk, r, pb);
+                if (t0 == 0 && g.bc_t < 0) sb = -sb;
+                hop_w<S, 3, -SF, true>(U, sbk, pb, sb, wb);
+            }
+            for (int t = t0; t < t0 + TC; ++t) {
+                const int s = c + Lxyz * t;
+                const bool wrap = (t == Lt - 1);
+                E en[12];
+                R sn = load_site_elems<S, NC>(in, wrap ? c : s + Lxyz, r, en);
+                SiteNbr nb;
+#pragma unroll
+                for (int mu = 0; mu < 3; ++mu) {
+                    nb.fwd[mu] = cf[mu] + Lxyz * t;
+                    nb.bwd[mu] = cb[mu] + Lxyz * t;
+                }
+                nb.fwd[3] = nb.bwd[3] = s;
+                nb.fwd_wrap_t = nb.bwd_wrap_t = false;
+                cplx<R> acc[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
+                hop_pair<0, DAG, PIN, NC, S>(g, U, in, s, nb, r, acc);
+                hop_pair<1, DAG, PIN, NC, S>(g, U, in, s, nb, r, acc);
+                hop_pair<2, DAG, PIN, NC, S>(g, U, in, s, nb, r, acc);
+                {
+                    const R sf = (wrap && g.bc_t < 0) ? -sn : sn;
+                    hop_acc<S, 3, SF, false>(U, s, en, sf, acc);
+                    pin_elems(en);
+                    asm volatile("" : "+v"(sn));
+                }
+                reconstruct_add<3, -SF>(acc, wb);
+                // the backward hop of the next step: U_t(s)^dag P psi(s)
+                hop_w<S, 3, -SF, true>(U, s, ec, sc, wb);
+                cplx<R> cc[12];
+                elems_to_cplx<S>(ec, cc);
+                if constexpr (S::scaled) {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) cc[k] = {cc[k].re * sc, cc[k].im * sc};
+                }
+                finish_site<S, NC, EPI>(diag, cc, acc, out, aux, s, r, d0r, d0i, d1r);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) ec[k] = en[k];
+                sc = sn;
+            }
+        }
+    }
+    if constexpr (EPI != EPI_NONE)
+        epi_reduce<EPI>(red, tid, rl, ry, r, N, NT, CB, d0r, d0i, d1r, d1i, partials, Lb, Gb);
 }
 
 }  // namespace wdt

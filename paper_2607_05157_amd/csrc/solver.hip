@@ -118,7 +118,7 @@ Shape site_shape(const wdt_lattice_s &lat, int N, int prec) {
     // about as many blocks as the GPU keeps resident (operator kernel occupancy)
     // FP64 sweeps are limited by L2 capacity (wide sites): one block per CU
     // keeps the XCD front small; narrower formats fill the CU
-    int per_cu = prec == WDT_FP64 ? 1 : op_blocks_per_cu(prec, N, sh.threads);
+    int per_cu = prec == WDT_FP64 ? 1 : op_blocks_per_cu(prec, N, sh.threads, 0);
     if (per_cu <= 0) per_cu = 2;
     const int64_t Gdef = (int64_t)device_cus() * per_cu;
     int64_t G = std::min<int64_t>(ngroups, tu.gmax > 0 ? tu.gmax : Gdef);
@@ -148,6 +148,102 @@ Shape site_shape(const wdt_lattice_s &lat, int N, int prec) {
     sh.bz = bz;
     sh.bt = lat.dims[3];
     sh.serial = tu.serial > 0;
+    // One site per wavefront (operator only; batches of 48 or 64): the links
+    // go through the scalar cache, which frees the vector memory pipeline
+    // that otherwise limits the operator.  Four blocks per CU: more resident
+    // blocks only widen each XCD's front beyond what its L2 holds.
+    sh.wps = (tu.wps > 0 || (tu.wps < 0 && tu.nt == 0)) && (N == 48 || N == 64);
+    if (sh.wps) {
+        int pw = op_blocks_per_cu(prec, N, 256, 2);
+        if (pw <= 0) pw = 2;
+        pw = std::min(pw, 4);
+        int64_t Gw = std::min<int64_t>((V + 3) / 4, tu.gmax > 0 ? tu.gmax : (int64_t)device_cus() * pw);
+        if (Gw >= 8 && tu.gmax <= 0) Gw = (Gw / 8) * 8;
+        sh.G = (int)std::max<int64_t>(Gw, 1);
+    }
+    // Brick order of the site sweep: each XCD's front, its share of the
+    // resident blocks, covers one slice of a compact brick of columns and
+    // moves through t, so spatial neighbours are read while their lines are
+    // in flight or fresh in the XCD's L2 and t-neighbours one slice later.
+    sh.sweep_brick = make_int4(0, 0, 0, 0);
+    if (tu.brick > 0) {
+        const int bx = tu.brick / 10000, by = (tu.brick / 100) % 100, bz = tu.brick % 100;
+        if (bx > 0 && by > 0 && bz > 0 && lat.dims[0] % bx == 0 && lat.dims[1] % by == 0 &&
+            lat.dims[2] % bz == 0)
+            sh.sweep_brick = make_int4(bx, by, bz, 0);
+    } else if (tu.brick == 0 && sh.wps) {
+        const int64_t front = (int64_t)std::max(1, sh.G / 8) * 4;  // sites per XCD front
+        int64_t best_vol = 0;
+        double best_surface = 1e30;
+        for (int bx = 1; bx <= lat.dims[0]; ++bx) {
+            if (lat.dims[0] % bx) continue;
+            for (int by = 1; by <= lat.dims[1]; ++by) {
+                if (lat.dims[1] % by) continue;
+                for (int bz = 1; bz <= lat.dims[2]; ++bz) {
+                    if (lat.dims[2] % bz) continue;
+                    const int64_t vol = (int64_t)bx * by * bz;
+                    if (vol > front) continue;
+                    const double surface = 2.0 / bx + 2.0 / by + 2.0 / bz;
+                    if (vol > best_vol || (vol == best_vol && surface < best_surface)) {
+                        sh.sweep_brick = make_int4(bx, by, bz, 0);
+                        best_vol = vol;
+                        best_surface = surface;
+                    }
+                }
+            }
+        }
+        // bricks far smaller than the front gain nothing over the plain order
+        if (best_vol * 4 < front) sh.sweep_brick = make_int4(0, 0, 0, 0);
+    }
+    // t-marching operator: chunks of tc slices over bricks of columns
+    sh.tc = 0;
+    sh.brick = make_int4(0, 0, 0, 0);
+    const int Lt = lat.dims[3];
+    const int tcq = tu.tchunk > 0 ? tu.tchunk : 0;
+    if (tcq > 0 && Lt % tcq == 0) {
+        int pm = op_blocks_per_cu(prec, N, sh.threads, 1);
+        if (pm <= 0) pm = 2;
+        const int64_t resident = tu.gmax > 0 ? tu.gmax : (int64_t)device_cus() * pm;
+        // columns one XCD marches at once: its share of the resident blocks
+        const int64_t cap = std::max<int64_t>(1, resident / 8) * SB;
+        int4 best = make_int4(0, 0, 0, 0);
+        double best_surface = 1e30;
+        int64_t best_vol = 0;
+        for (int bx = SB; bx <= lat.dims[0]; bx += SB) {
+            if (lat.dims[0] % bx) continue;
+            for (int by = 1; by <= lat.dims[1]; ++by) {
+                if (lat.dims[1] % by) continue;
+                for (int bz = 1; bz <= lat.dims[2]; ++bz) {
+                    if (lat.dims[2] % bz) continue;
+                    const int64_t vol = (int64_t)bx * by * bz;
+                    if (vol > cap) continue;
+                    // neighbour reads that leave the brick, per site
+                    const double surface = 2.0 / bx + 2.0 / by + 2.0 / bz;
+                    if (vol > best_vol || (vol == best_vol && surface < best_surface)) {
+                        best = make_int4(bx, by, bz, 0);
+                        best_vol = vol;
+                        best_surface = surface;
+                    }
+                }
+            }
+        }
+        if (best_vol > 0) {
+            sh.tc = tcq;
+            sh.brick = best;
+            const int64_t upb = best_vol / SB;
+            const int64_t units = (V / Lt) / SB * (Lt / tcq);
+            int64_t Gm;
+            if (tu.gmax > 0) {
+                Gm = std::min<int64_t>(units, tu.gmax);
+            } else {
+                // whole bricks per XCD round
+                const int64_t k = std::max<int64_t>(1, resident / (8 * upb));
+                Gm = std::min<int64_t>(units, 8 * upb * k);
+                if (Gm >= 8) Gm = (Gm / 8) * 8;
+            }
+            sh.G = (int)std::max<int64_t>(Gm, 1);
+        }
+    }
     return sh;
 }
 
@@ -155,6 +251,11 @@ Geom shaped_geom(const wdt_lattice_s &lat, const Shape &sh) {
     Geom g = lat.geom();
     g.bz = sh.bz;
     g.bt = sh.bt;
+    if (sh.tc == 0 && sh.sweep_brick.x > 0) {
+        g.bx = sh.sweep_brick.x;
+        g.by = sh.sweep_brick.y;
+        g.bz = sh.sweep_brick.z;
+    }
     return g;
 }
 

@@ -70,6 +70,12 @@ def main(argv=None):
     ap.add_argument("--bz", type=int, nargs="+", default=[0])
     ap.add_argument("--serial", type=int, nargs="+", default=[-1],
                     help="operator blocks sweep RHS tiles in turn: 1 on, 0 off, -1 automatic")
+    ap.add_argument("--tchunk", type=int, nargs="+", default=[-1],
+                    help="operator marches along t in chunks of this many slices (0 off)")
+    ap.add_argument("--wps", type=int, nargs="+", default=[-1],
+                    help="operator: one site per wavefront (1 on, 0 off, -1 automatic)")
+    ap.add_argument("--brick", nargs="+", default=["auto"],
+                    help="site-sweep brick order: x,y,z extents, 'auto' or 'off'")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
@@ -96,15 +102,19 @@ def main(argv=None):
             s = torch.ones(V * N, device="cuda", dtype=torch.float32)
             x = torch.cat([h.half().view(torch.uint8), s.view(torch.uint8)])
         y = torch.zeros_like(x)
-        for nt, sb, gm, bz, se in itertools.product(a.tiles, a.sb, a.gmax, a.bz, a.serial):
-            W.set_launch_shape(nt, sb, gm, bz, se)
+        bricks = [(0, 0, 0) if b == "auto" else (-1, -1, -1) if b == "off"
+                  else tuple(int(v) for v in b.split(",")) for b in a.brick]
+        for nt, sb, gm, bz, se, tc, br, wp in itertools.product(
+                a.tiles, a.sb, a.gmax, a.bz, a.serial, a.tchunk, bricks, a.wps):
+            W.set_launch_shape(nt, sb, gm, bz, se, tc, br, wp)
             ms = time_apply(W, g, lat, x, y, N, prec, a.reps, torch)
             gbps = alg_bytes(V, N, prec) / (ms * 1e-3) / 1e9
             r = dict(prec=pname, rhs_tile=nt, sites_per_block=sb, max_blocks=gm, z_slab=bz,
-                     serial=se, ms=round(ms, 4), gbps=round(gbps, 1))
+                     serial=se, tchunk=tc, brick=list(br), wps=wp, ms=round(ms, 4),
+                     gbps=round(gbps, 1))
             results.append(r)
             print(json.dumps(r), flush=True)
-        W.set_launch_shape(0, 0, 0, 0, -1)
+        W.set_launch_shape()
     best = {}
     for r in results:
         if r["prec"] not in best or r["gbps"] > best[r["prec"]]["gbps"]:

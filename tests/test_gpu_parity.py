@@ -37,6 +37,26 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).cuda()
 
 
+def fp16_batch(psi):
+    """[V, 12, N] complex -> device FP16 batch (half2 [V,12,N], then the float
+    scale [V,N]), built on the host."""
+    V, _, N = psi.shape
+    sc = np.max(np.maximum(np.abs(psi.real), np.abs(psi.imag)), axis=1)  # [V,N]
+    h = np.empty((V, 12, N, 2), dtype=np.float16)
+    h[..., 0] = (psi.real / sc[:, None, :]).astype(np.float16)
+    h[..., 1] = (psi.imag / sc[:, None, :]).astype(np.float16)
+    buf = np.concatenate([h.view(np.uint8).ravel(), sc.astype(np.float32).view(np.uint8).ravel()])
+    return torch.from_numpy(buf).cuda()
+
+
+def from_fp16(out, V, N):
+    ob = out.cpu().numpy()
+    nh = V * 12 * N * 4
+    hh = ob[:nh].view(np.float16).reshape(V, 12, N, 2).astype(np.float64)
+    s2 = ob[nh:].view(np.float32).reshape(V, N).astype(np.float64)
+    return (hh[..., 0] + 1j * hh[..., 1]) * s2[:, None, :]
+
+
 def rand_batch(V, N, seed):
     rng = np.random.default_rng(seed)
     return rng.standard_normal((V, 12, N)) + 1j * rng.standard_normal((V, 12, N))
@@ -116,20 +136,10 @@ def test_apply_D_low_precision(prec, tol):
         W.apply_D(g, 0.05, x, out, N, p)
         got = out.cpu().numpy().astype(np.complex128)
     else:
-        # FP16 batches: half2 [V,12,N] then float scale [V,N]; build on host
-        sc = np.max(np.maximum(np.abs(psi.real), np.abs(psi.imag)), axis=1)  # [V,N]
-        h = np.empty((V, 12, N, 2), dtype=np.float16)
-        h[..., 0] = (psi.real / sc[:, None, :]).astype(np.float16)
-        h[..., 1] = (psi.imag / sc[:, None, :]).astype(np.float16)
-        buf = np.concatenate([h.view(np.uint8).ravel(), sc.astype(np.float32).view(np.uint8).ravel()])
-        x = torch.from_numpy(buf).cuda()
+        x = fp16_batch(psi)
         out = torch.zeros_like(x)
         W.apply_D(g, 0.05, x, out, N, p)
-        ob = out.cpu().numpy()
-        nh = V * 12 * N * 4
-        hh = ob[:nh].view(np.float16).reshape(V, 12, N, 2).astype(np.float64)
-        s2 = ob[nh:].view(np.float32).reshape(V, N).astype(np.float64)
-        got = (hh[..., 0] + 1j * hh[..., 1]) * s2[:, None, :]
+        got = from_fp16(out, V, N)
     err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
     assert err < tol, err
 
@@ -319,11 +329,18 @@ def test_force_matches_oracle():
 # ---------------------------------------------------------------------------
 # launch shapes: every tuner setting computes the same operator and solve
 
-SHAPES = [  # (rhs_tile, sites_per_block, max_blocks, z_slab, serial_tiles)
-    (8, 0, 0, 0, 1),       # tiles swept in turn, ragged last tile (N = 20)
-    (8, 0, 24, 1, 1),      # few blocks, thinnest slab
-    (16, 0, 8, 2, 0),      # tiles side by side
-    (6, 5, 40, 0, 1),      # odd tile and block shape
+SHAPES = [  # (rhs_tile, sites_per_block, max_blocks, z_slab, serial_tiles, t_chunk[, brick])
+    (8, 0, 0, 0, 1, 0),        # tiles swept in turn, ragged last tile (N = 20)
+    (8, 0, 24, 1, 1, 0),       # few blocks, thinnest slab
+    (16, 0, 8, 2, 0, 0),       # tiles side by side
+    (6, 5, 40, 0, 1, 0),       # odd tile and block shape
+    (0, 4, 0, 0, -1, 2),       # t-march, 4 columns per block, chunks of 2 slices
+    (8, 2, 0, 0, 0, 1),        # t-march, one slice per chunk, ragged RHS tile
+    (0, 4, 16, 0, -1, 6),      # t-march over all of Lt = 6 with 16 blocks (Lt = 4: site sweep)
+    (16, 3, 0, 0, -1, 2),      # 3 columns per block cannot tile Lx = 4: site sweep
+    (0, 0, 0, 0, -1, 0, (2, 2, 2)),   # site sweep in brick order
+    (8, 0, 16, 0, 0, 0, (4, 2, 1)),   # brick order, flat bricks, few blocks
+    (0, 0, 0, 0, -1, 0, (3, 2, 2)),   # brick not dividing Lx: plain order
 ]
 
 
@@ -358,4 +375,45 @@ def test_launch_shapes_operator_and_solve(c1, shape):
             xs = x.cpu().numpy().reshape(-1, N)
             assert np.max(np.linalg.norm(xs - X, axis=0) / np.linalg.norm(X, axis=0)) < bar
     finally:
-        W.set_launch_shape(0, 0, 0, 0, -1)
+        W.set_launch_shape()
+
+
+@pytest.mark.parametrize("N", [48, 64])
+def test_wave_per_site_operator_and_solve(c1, N):
+    """One site per wavefront (64 RHS lanes, links through the scalar cache):
+    the operator in FP64 and FP16 against the oracle, and a mixed solve."""
+    say("wave per site", N)
+    dims = (4, 4, 2, 6)
+    V = int(np.prod(dims))
+    U = gauge_field(dims, 0.5, seed=21)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    psi = rand_batch(V, N, 8)
+    try:
+        for brick in ((0, 0, 0), (2, 2, 1)):
+            W.set_launch_shape(wave_per_site=1, brick=brick)
+            for dagger in (False, True):
+                ref = dirac.apply_D(U, 0.07, psi, dims, -1, dagger=dagger)
+                out = lat.new_batch(N)
+                W.apply_D(g, 0.07, to_dev(psi), out, N, W.FP64, dagger)
+                err = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(np.abs(ref))
+                assert err < 1e-14, (brick, dagger, err)
+            ref = dirac.apply_D(U, 0.07, psi, dims, -1)
+            x = fp16_batch(psi)
+            out = torch.zeros_like(x)
+            W.apply_D(g, 0.07, x, out, N, W.FP16)
+            err = np.max(np.abs(from_fp16(out, V, N) - ref)) / np.max(np.abs(ref))
+            assert err < 4e-3, (brick, err)
+        dims1, m0, U1, Dinv = c1
+        lat1 = W.Lattice(dims1, -1)
+        g1 = W.Gauge(lat1, U1)
+        b = lat1.new_batch(N)
+        W.sources(lat1, W.source_descs(list(range(N))), b)
+        x = lat1.new_batch(N)
+        rc, st = W.solve(g1, m0, b, x, N, tol=1e-10, prec=W.FP16)
+        assert all(s["converged"] for s in st)
+        X = Dinv @ b.cpu().numpy().reshape(-1, N)
+        xs = x.cpu().numpy().reshape(-1, N)
+        assert np.max(np.linalg.norm(xs - X, axis=0) / np.linalg.norm(X, axis=0)) < 1e-8
+    finally:
+        W.set_launch_shape()
