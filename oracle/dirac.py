@@ -65,17 +65,22 @@ def apply_D_sites(U, m0, psi, dims, sites, bc_t=-1, dagger=False):
     """(D psi)(x) (or D^dag) at the listed sites only, straight from the
     definition above: for lattices too large for a whole matrix.
 
-    psi: [V, 12, N] array; returns [len(sites), 12, N]."""
+    psi: [V, 12, N] array, or a function site -> [12, N] row (for inputs too
+    large to hold); returns [len(sites), 12, N]."""
     from .geometry import coords
     U = np.asarray(U)
-    psi = np.asarray(psi)
+    if callable(psi):
+        row = psi
+    else:
+        arr = np.asarray(psi)
+        row = lambda s: arr[s]
     c = coords(dims)
     L = np.asarray(dims)
     strides = [1, dims[0], dims[0] * dims[1], dims[0] * dims[1] * dims[2]]
     out = []
     sgn = +1 if dagger else -1          # forward projector (1 + sgn gamma)
     for s in sites:
-        acc = (4.0 + m0) * psi[s]
+        acc = (4.0 + m0) * row(s)
         for mu in range(4):
             cm = c[s, mu]
             f = s + strides[mu] if cm < L[mu] - 1 else s - (L[mu] - 1) * strides[mu]
@@ -84,8 +89,8 @@ def apply_D_sites(U, m0, psi, dims, sites, bc_t=-1, dagger=False):
             phb = bc_t if (mu == 3 and cm == 0) else 1.0
             Pf = ID4 + sgn * GAMMA[mu]
             Pb = ID4 - sgn * GAMMA[mu]
-            hf = np.einsum("st,ab,tbn->san", Pf, U[s, mu], psi[f].reshape(4, 3, -1))
-            hb = np.einsum("st,ba,tbn->san", Pb, np.conj(U[b, mu]), psi[b].reshape(4, 3, -1))
+            hf = np.einsum("st,ab,tbn->san", Pf, U[s, mu], row(f).reshape(4, 3, -1))
+            hb = np.einsum("st,ba,tbn->san", Pb, np.conj(U[b, mu]), row(b).reshape(4, 3, -1))
             acc = acc - 0.5 * (phf * hf + phb * hb).reshape(12, -1)
         out.append(acc)
     return np.stack(out)

@@ -73,6 +73,16 @@ def rademacher(seed, n):
     return np.where((z >> np.uint64(63)) == 0, 1.0, -1.0)
 
 
+def rademacher_at(seed, g):
+    """eta_seed at the global indices g (an integer array): the same formula
+    as rademacher(), for vectors too long to form whole."""
+    with np.errstate(over="ignore"):
+        c = (np.uint64(seed) << np.uint64(40)) + np.asarray(g, dtype=np.uint64)
+        z = (c + np.uint64(1)) * np.uint64(GOLDEN)
+        z = _mix64_np(z)
+    return np.where((z >> np.uint64(63)) == 0, 1.0, -1.0)
+
+
 def probing_vector(dims, seed, colours=None, colour=None, component=-1, t0=-1):
     """Source vector [V, 12] (float64 +-1 / 0).
 

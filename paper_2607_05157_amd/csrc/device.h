@@ -226,6 +226,32 @@ __device__ __forceinline__ void elems_to_cplx(const typename S::elem (&e)[12],
     }
 }
 
+// load_site for data read once (non-temporal loads: the lines are marked
+// for early eviction and do not push out neighbour lines still to be re-read)
+template <class S, int NC = 0>
+__device__ __forceinline__ void load_site_once(const SpinorPtr<S> &sp, int site, int r,
+                                               cplx<typename S::real> (&v)[12]) {
+    const int N = batch_n<S, NC>(sp);
+    const typename S::elem *q = sp.p + (size_t)site * 12 * N + r;
+    using R = typename S::real;
+    if constexpr (S::scaled) {
+        const float sc = __builtin_nontemporal_load(sp.scale + (size_t)site * N + r);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            unsigned u = __builtin_nontemporal_load(reinterpret_cast<const unsigned *>(q + k * N));
+            __half2 h;
+            __builtin_memcpy(&h, &u, 4);
+            const float2 f = __half22float2(h);
+            v[k] = {f.x * sc, f.y * sc};
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            v[k] = {__builtin_nontemporal_load(&q[k * N].x), __builtin_nontemporal_load(&q[k * N].y)};
+    }
+    (void)sizeof(R);
+}
+
 template <class S, int NC = 0>
 __device__ __forceinline__ void load_site(const SpinorPtr<S> &sp, int site, int r,
                                           cplx<typename S::real> (&v)[12]) {

@@ -41,13 +41,13 @@ __global__ __launch_bounds__(256) void k_dslash(Geom g, const typename S::link *
                                       xcd_block(blockIdx.x, gridDim.x), gridDim.x);
 }
 
-template <class S, int NC, bool DAG, int EPI>
+template <class S, int NC, bool DAG, int EPI, bool WPS = false>
 __global__ __launch_bounds__(256) void k_dslash_march(Geom g, const typename S::link *__restrict__ U,
                                                       typename S::real diag, SpinorPtr<S> in,
                                                       SpinorPtr<S> out, SpinorPtr<S> aux, int N,
                                                       int NT, int CB, int TC, int4 B,
                                                       double2 *__restrict__ partials) {
-    dslash_march_body<S, NC, DAG, EPI>(g, U, diag, in, out, aux, N, NT, CB, TC, B, partials,
+    dslash_march_body<S, NC, DAG, EPI, WPS>(g, U, diag, in, out, aux, N, NT, CB, TC, B, partials,
                                        blockIdx.y, xcd_block(blockIdx.x, gridDim.x), gridDim.x);
 }
 
@@ -69,6 +69,11 @@ static void launch_k(dim3 grid, int threads, hipStream_t stream, const Geom &g,
                                g, U, diag, pin_, pout, paux, N, NT, SB, part, serial_tiles);
             return;
         }
+        if (wps && tc > 0) {
+            hipLaunchKernelGGL((k_dslash_march<S, NC, DAG, EPI, true>), grid, dim3(threads), 0,
+                               stream, g, U, diag, pin_, pout, paux, N, NT, SB, tc, brick, part);
+            return;
+        }
     }
     if (tc > 0)
         hipLaunchKernelGGL((k_dslash_march<S, NC, DAG, EPI>), grid, dim3(threads), 0, stream, g,
@@ -85,7 +90,7 @@ static int launch_t(const wdt_gauge_s *gf, double m0, const void *in, void *out,
     const Geom g = shaped_geom(gf->lat, sh);
     const int V = g.V;
     // one site per wavefront: 64 lanes per site, four sites per block
-    const bool wps = sh.wps && sh.tc == 0 && (nc_of(N) == 48 || nc_of(N) == 64);
+    const bool wps = sh.wps && (nc_of(N) == 48 || nc_of(N) == 64);
     const int NT = wps ? 64 : sh.NT, SB = wps ? 4 : sh.SB, threads = wps ? 256 : sh.threads;
     const int tiles = (N + NT - 1) / NT;
     const dim3 grid(sh.G, (sh.serial && sh.tc == 0) ? 1 : tiles);
@@ -168,6 +173,9 @@ static int occ_t(int threads, int mode) {
     else if (mode == 2 && (NC == 48 || NC == 64))
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &nb, k_dslash<S, NC, false, EPI_DOT_AUX, (NC == 48 || NC == 64)>, threads, 0);
+    else if (mode == 3 && (NC == 48 || NC == 64))
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, k_dslash_march<S, NC, false, EPI_DOT_AUX, (NC == 48 || NC == 64)>, threads, 0);
     else
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &nb, k_dslash<S, NC, false, EPI_DOT_AUX>, threads, 0);

@@ -110,7 +110,8 @@ struct Shape {
 };
 Shape site_shape(const wdt_lattice_s &lat, int N, int prec);
 // Resident blocks per CU of the operator kernel for (prec, N, block size).
-// mode: 0 site sweep, 1 t-march, 2 site sweep with one site per wavefront
+// mode: 0 site sweep, 1 t-march, 2 site sweep with one site per wavefront,
+// 3 t-march with one site (column) per wavefront
 int op_blocks_per_cu(int prec, int N, int threads, int mode);
 // The lattice geometry with the processing order of a shape.
 wdt::Geom shaped_geom(const wdt_lattice_s &lat, const Shape &sh);

@@ -292,6 +292,10 @@ template <class S> struct OpPin { static constexpr int value = 1; };
 #ifndef WDT_OP_STREAM_STORES
 #define WDT_OP_STREAM_STORES 1
 #endif
+// The epilogue's extra vector (rhat, or b for the residual) is read once.
+#ifndef WDT_AUX_LOAD
+#define WDT_AUX_LOAD load_site_once
+#endif
 
 // ---------------------------------------------------------------------------
 // FP16 operator arithmetic.  The half spinor is formed in packed half
@@ -506,7 +510,7 @@ __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::lin
                 o[k] = {diag * c[k].re - R(0.5) * acc[k].re, diag * c[k].im - R(0.5) * acc[k].im};
             if constexpr (EPI == EPI_RESID) {
                 cplx<R> b[12];
-                load_site<S, NC>(aux, s, r, b);
+                WDT_AUX_LOAD<S, NC>(aux, s, r, b);
 #pragma unroll
                 for (int k = 0; k < 12; ++k) {
                     o[k] = csub(b[k], o[k]);
@@ -515,7 +519,7 @@ __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::lin
                 }
             } else if constexpr (EPI == EPI_DOT_AUX) {
                 cplx<R> a[12];
-                load_site<S, NC>(aux, s, r, a);
+                WDT_AUX_LOAD<S, NC>(aux, s, r, a);
 #pragma unroll
                 for (int k = 0; k < 12; ++k) {
                     d0r += (double)a[k].re * o[k].re + (double)a[k].im * o[k].im;
@@ -591,7 +595,7 @@ __device__ __forceinline__ void finish_site(typename S::real diag, const cplx<ty
         o[k] = {diag * c[k].re - R(0.5) * acc[k].re, diag * c[k].im - R(0.5) * acc[k].im};
     if constexpr (EPI == EPI_RESID) {
         cplx<R> b[12];
-        load_site<S, NC>(aux, s, r, b);
+        WDT_AUX_LOAD<S, NC>(aux, s, r, b);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             o[k] = csub(b[k], o[k]);
@@ -600,7 +604,7 @@ __device__ __forceinline__ void finish_site(typename S::real diag, const cplx<ty
         }
     } else if constexpr (EPI == EPI_DOT_AUX) {
         cplx<R> a[12];
-        load_site<S, NC>(aux, s, r, a);
+        WDT_AUX_LOAD<S, NC>(aux, s, r, a);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             d0r += (double)a[k].re * o[k].re + (double)a[k].im * o[k].im;
@@ -631,7 +635,7 @@ __device__ __forceinline__ void finish_site(typename S::real diag, const cplx<ty
 // units, so what an XCD marches through at once is a whole brick: the six
 // spatial reads of a site find the slice its neighbours loaded one step
 // earlier in that XCD's L2, except across the brick's faces.
-template <class S, int NC, bool DAG, int EPI>
+template <class S, int NC, bool DAG, int EPI, bool WPS = false>
 __device__ __forceinline__ void dslash_march_body(const Geom &g, const typename S::link *__restrict__ U,
                                                   typename S::real diag, SpinorPtr<S> in,
                                                   SpinorPtr<S> out, SpinorPtr<S> aux, int N,
@@ -644,8 +648,8 @@ __device__ __forceinline__ void dslash_march_body(const Geom &g, const typename 
     constexpr int SF = DAG ? +1 : -1;
     __shared__ double2 red[2][256];
     const int tid = threadIdx.x;
-    const int rl = tid % NT;
-    const int ry = tid / NT;
+    const int rl = WPS ? (tid & 63) : tid % NT;
+    const int ry = WPS ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid / NT;
     const int r = tile * NT + rl;
     const bool live = (ry < CB) && (r < N);
     const int L0 = g.L[0], L1 = g.L[1], L2 = g.L[2], Lt = g.L[3];

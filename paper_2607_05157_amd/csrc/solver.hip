@@ -154,9 +154,7 @@ Shape site_shape(const wdt_lattice_s &lat, int N, int prec) {
     // blocks only widen each XCD's front beyond what its L2 holds.
     sh.wps = (tu.wps > 0 || (tu.wps < 0 && tu.nt == 0)) && (N == 48 || N == 64);
     if (sh.wps) {
-        int pw = op_blocks_per_cu(prec, N, 256, 2);
-        if (pw <= 0) pw = 2;
-        pw = std::min(pw, 4);
+        const int pw = 4;
         int64_t Gw = std::min<int64_t>((V + 3) / 4, tu.gmax > 0 ? tu.gmax : (int64_t)device_cus() * pw);
         if (Gw >= 8 && tu.gmax <= 0) Gw = (Gw / 8) * 8;
         sh.G = (int)std::max<int64_t>(Gw, 1);
@@ -200,16 +198,18 @@ Shape site_shape(const wdt_lattice_s &lat, int N, int prec) {
     sh.brick = make_int4(0, 0, 0, 0);
     const int Lt = lat.dims[3];
     const int tcq = tu.tchunk > 0 ? tu.tchunk : 0;
+    // columns per block: 4 with one column per wavefront, else the site tile
+    const int CBm = sh.wps ? 4 : SB;
     if (tcq > 0 && Lt % tcq == 0) {
-        int pm = op_blocks_per_cu(prec, N, sh.threads, 1);
+        int pm = sh.wps ? op_blocks_per_cu(prec, N, 256, 3) : op_blocks_per_cu(prec, N, sh.threads, 1);
         if (pm <= 0) pm = 2;
         const int64_t resident = tu.gmax > 0 ? tu.gmax : (int64_t)device_cus() * pm;
         // columns one XCD marches at once: its share of the resident blocks
-        const int64_t cap = std::max<int64_t>(1, resident / 8) * SB;
+        const int64_t cap = std::max<int64_t>(1, resident / 8) * CBm;
         int4 best = make_int4(0, 0, 0, 0);
         double best_surface = 1e30;
         int64_t best_vol = 0;
-        for (int bx = SB; bx <= lat.dims[0]; bx += SB) {
+        for (int bx = CBm; bx <= lat.dims[0]; bx += CBm) {
             if (lat.dims[0] % bx) continue;
             for (int by = 1; by <= lat.dims[1]; ++by) {
                 if (lat.dims[1] % by) continue;
@@ -230,8 +230,8 @@ Shape site_shape(const wdt_lattice_s &lat, int N, int prec) {
         if (best_vol > 0) {
             sh.tc = tcq;
             sh.brick = best;
-            const int64_t upb = best_vol / SB;
-            const int64_t units = (V / Lt) / SB * (Lt / tcq);
+            const int64_t upb = best_vol / CBm;
+            const int64_t units = (V / Lt) / CBm * (Lt / tcq);
             int64_t Gm;
             if (tu.gmax > 0) {
                 Gm = std::min<int64_t>(units, tu.gmax);

@@ -390,8 +390,8 @@ def test_wave_per_site_operator_and_solve(c1, N):
     g = W.Gauge(lat, U)
     psi = rand_batch(V, N, 8)
     try:
-        for brick in ((0, 0, 0), (2, 2, 1)):
-            W.set_launch_shape(wave_per_site=1, brick=brick)
+        for brick, tc in (((0, 0, 0), -1), ((2, 2, 1), -1), ((0, 0, 0), 2), ((0, 0, 0), 6)):
+            W.set_launch_shape(wave_per_site=1, brick=brick, t_chunk=tc)
             for dagger in (False, True):
                 ref = dirac.apply_D(U, 0.07, psi, dims, -1, dagger=dagger)
                 out = lat.new_batch(N)
@@ -409,11 +409,59 @@ def test_wave_per_site_operator_and_solve(c1, N):
         g1 = W.Gauge(lat1, U1)
         b = lat1.new_batch(N)
         W.sources(lat1, W.source_descs(list(range(N))), b)
-        x = lat1.new_batch(N)
-        rc, st = W.solve(g1, m0, b, x, N, tol=1e-10, prec=W.FP16)
-        assert all(s["converged"] for s in st)
         X = Dinv @ b.cpu().numpy().reshape(-1, N)
-        xs = x.cpu().numpy().reshape(-1, N)
-        assert np.max(np.linalg.norm(xs - X, axis=0) / np.linalg.norm(X, axis=0)) < 1e-8
+        for tc in (-1, 2):
+            W.set_launch_shape(wave_per_site=1, t_chunk=tc)
+            x = lat1.new_batch(N)
+            rc, st = W.solve(g1, m0, b, x, N, tol=1e-10, prec=W.FP16)
+            assert all(s["converged"] for s in st)
+            xs = x.cpu().numpy().reshape(-1, N)
+            assert np.max(np.linalg.norm(xs - X, axis=0) / np.linalg.norm(X, axis=0)) < 1e-8
     finally:
         W.set_launch_shape()
+
+
+def test_apply_D_24c48_64rhs_sampled():
+    """The 24^3x48 workload's operator (64 RHS, one site per wavefront) in FP64
+    and FP16 on Rademacher batches made by the library's source kernel:
+    sampled sites against the oracle's row-by-row definition, with the input
+    rows regenerated on the host by the oracle's own noise generator."""
+    from synth.workloads import workload
+    cfg = workload("loop_24c48_d4")
+    dims, N, m0 = cfg["dims"], 64, cfg["m0"]
+    say("apply_D 24^3x48", dims, N)
+    V = int(np.prod(dims))
+    U = gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    seeds = list(range(700, 700 + N))
+
+    def rows(s):
+        gidx = 12 * s + np.arange(12)
+        return np.stack([noise.rademacher_at(k, gidx) for k in seeds], axis=1).astype(complex)
+
+    rng = np.random.default_rng(11)
+    Lxyz = dims[0] * dims[1] * dims[2]
+    sites = [int(v) for v in rng.integers(0, V, 12)] + [0, V - 1, Lxyz * (dims[3] - 1), Lxyz - 1]
+    ref = dirac.apply_D_sites(U, m0, rows, dims, sites, -1)
+    idx = torch.tensor(sites, device="cuda")
+    # FP64
+    x = lat.new_batch(N)
+    W.sources(lat, W.source_descs(seeds), x)
+    out = lat.new_batch(N)
+    W.apply_D(g, m0, x, out, N, W.FP64)
+    got = out.index_select(0, idx).cpu().numpy()
+    assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(ref))
+    del x, out
+    # FP16 (sources are exact in FP16: +-1 with unit scale)
+    xh = lat.new_batch(N, prec=W.FP16)
+    W.sources(lat, W.source_descs(seeds), xh, prec=W.FP16)
+    oh = torch.zeros_like(xh)
+    W.apply_D(g, m0, xh, oh, N, W.FP16)
+    w = oh.view(torch.int32)
+    comp = (idx[:, None] * (12 * N) + torch.arange(12 * N, device="cuda")[None, :]).reshape(-1)
+    sc = (V * 12 * N + idx[:, None] * N + torch.arange(N, device="cuda")[None, :]).reshape(-1)
+    halves = w.index_select(0, comp).cpu().numpy().view(np.float16).reshape(len(sites), 12, N, 2)
+    scale = w.index_select(0, sc).cpu().numpy().view(np.float32).reshape(len(sites), 1, N)
+    goth = (halves[..., 0].astype(np.float64) + 1j * halves[..., 1].astype(np.float64)) * scale
+    assert np.max(np.abs(goth - ref)) < 4e-3 * np.max(np.abs(ref))

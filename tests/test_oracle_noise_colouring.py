@@ -105,3 +105,10 @@ def _first_valid_python(dims, d):
 @pytest.mark.parametrize("dims,d", [((4, 2, 2, 4), 1), ((4, 4, 2, 2), 2), ((3, 2, 2, 4), 1)])
 def test_search_is_first_valid(dims, d):
     assert colouring.search(dims, d) == _first_valid_python(dims, d)
+
+
+def test_rademacher_at_matches_whole_vector():
+    from oracle import noise
+    g = np.array([0, 1, 5, 1000, 12 * 300 - 1])
+    for seed in (0, 3, 2 ** 24 - 1):
+        assert np.array_equal(noise.rademacher_at(seed, g), noise.rademacher(seed, 12 * 300)[g])

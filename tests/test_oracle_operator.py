@@ -158,3 +158,16 @@ def test_sampled_rows_match_sparse(dagger):
     sites = [0, 3, 17, 40, V - 1, 8, 88]
     part = dirac.apply_D_sites(U, 0.3, psi, dims, sites, -1, dagger=dagger)
     assert np.max(np.abs(part - full[sites])) < 1e-14
+
+
+def test_apply_D_sites_row_function_matches_array():
+    """The row-provider form of the sampled operator gives the same rows."""
+    dims, N = (4, 2, 2, 4), 3
+    V = int(np.prod(dims))
+    U = gauge_field(dims, 0.4, seed=12)
+    rng = np.random.default_rng(3)
+    psi = rng.standard_normal((V, 12, N)) + 1j * rng.standard_normal((V, 12, N))
+    sites = [0, 5, V - 1, 17]
+    a = dirac.apply_D_sites(U, 0.1, psi, dims, sites)
+    b = dirac.apply_D_sites(U, 0.1, lambda s: psi[s], dims, sites)
+    assert np.array_equal(a, b)
