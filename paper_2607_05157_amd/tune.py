@@ -29,7 +29,9 @@ def alg_bytes(V, N, prec):
 
 
 def time_apply(W, g, lat, x, y, N, prec, reps, torch):
-    W.apply_D(g, 0.02, x, y, N, prec)
+    # warm-up: the first launches of a shape run on a cold GPU (clocks, caches)
+    for _ in range(max(3, reps // 2)):
+        W.apply_D(g, 0.02, x, y, N, prec)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
