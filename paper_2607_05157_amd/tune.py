@@ -1,7 +1,8 @@
 """Launch-shape tuner for the multi-RHS operator kernel.
 
 Times wdt_apply_D over a grid of launch shapes (RHS tile, sites per block,
-blocks per tile) for one lattice, batch size and precision, and reports the
+blocks per tile, z-slab, tile order, t-march chunk, brick order, one site per
+wavefront) for one lattice, batch size and precision, and reports the
 algorithmic bandwidth of each (bytes: every input spinor read once, every
 output written once, the links once per launch).  Also times a plain device
 copy of the same size as a bandwidth reference.
@@ -21,7 +22,7 @@ if __name__ == "__main__":
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
 SITE_BYTES = {0: 192, 1: 96, 2: 52}
-LINK_BYTES = {0: 144, 1: 72, 2: 72}  # FP16 storage reads FP32 links
+LINK_BYTES = {0: 144, 1: 72, 2: 72}  # FP32 links; FP16: two packed halves per element
 
 
 def alg_bytes(V, N, prec):
