@@ -100,7 +100,7 @@ static int launch_t(const wdt_gauge_s *gf, double m0, const void *in, void *out,
     SpinorPtr<S> paux = make_spinor<S>(const_cast<void *>(aux), V, N);
     const int prec = prec_of<S>();
     static const char *names[3] = {"dslash_fp64", "dslash_fp32", "dslash_fp16"};
-    const int nvec = (EPI == EPI_DOT_AUX || EPI == EPI_RESID) ? 3 : 2;
+    const int nvec = (EPI == EPI_DOT_AUX || EPI == EPI_RESID || EPI == EPI_DOT_TSR) ? 3 : 2;
     ProfScope prof(names[prec],
                    (double)V * ((double)N * nvec * site_bytes(prec) + 4.0 * link_bytes(prec)),
                    stream);
@@ -140,6 +140,7 @@ static int launch_p(const wdt_gauge_s *gf, double m0, int dagger, int epi, const
         WDT_EPI_CASE(EPI_DOT_AUX)
         WDT_EPI_CASE(EPI_DOT_TS)
         WDT_EPI_CASE(EPI_RESID)
+        WDT_EPI_CASE(EPI_DOT_TSR)
         default:
             return set_error(WDT_EINVAL, "bad operator epilogue %d", epi);
     }

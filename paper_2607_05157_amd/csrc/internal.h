@@ -127,12 +127,13 @@ struct LaunchTuning {
 LaunchTuning &tuning();
 
 // Epilogues of the operator kernel.
-enum Epi { EPI_NONE = 0, EPI_DOT_AUX = 1, EPI_DOT_TS = 2, EPI_RESID = 3 };
+enum Epi { EPI_NONE = 0, EPI_DOT_AUX = 1, EPI_DOT_TS = 2, EPI_RESID = 3, EPI_DOT_TSR = 4 };
 
 // out = D in (or D^dag in); optional fused per-RHS dot partials written to
 // partials[(d*G + block)*N + r] as complex doubles.
 //  EPI_DOT_AUX: d0 = aux^dag out
 //  EPI_DOT_TS:  d0 = out^dag in, d1 = ||out||^2
+//  EPI_DOT_TSR: as EPI_DOT_TS, and d2 = aux^dag out
 //  EPI_RESID:   out = aux - D in; d0 = ||out||^2, d1 = ||aux||^2
 int launch_dslash(const wdt_gauge_s *g, double m0, int prec, int dagger, int epi,
                   const void *in, void *out, const void *aux, int N, double2 *partials,

@@ -8,6 +8,7 @@ namespace wdt {
 
 struct RhsState {
     double2 rho, alpha, omega, beta;
+    double2 rv;  // rhat^dag v of the current iteration (fused updates)
     double rr, bb, tol2;
     int active;  // 1 while the RHS is iterating
     int flag;    // 0 running, 1 converged, 2 breakdown
@@ -81,6 +82,7 @@ __device__ __forceinline__ void scalar_alpha_body(RhsState *st, const double2 *p
                 s.alpha = make_double2(0, 0);
             } else {
                 s.alpha = cdiv(s.rho, rv);
+                s.rv = rv;
             }
         } else {
             s.alpha = make_double2(0, 0);
@@ -226,6 +228,110 @@ __device__ __forceinline__ void update_p_body(const Geom &g, int N, int NT, int 
     for (int k = 0; k < 12; ++k) p[k] = cadd(x[k], cmul(b, csub(p[k], cmul(w, v[k]))));
     store_site<S>(pv, s, r, p);
     SITE_LOOP_END
+}
+
+// Fused form of the end of an iteration, for the inner solves of the mixed
+// solver: the new shadow product comes from the recurrence
+//   rhat^dag r_new = rhat^dag s - omega rhat^dag t = rho - alpha rhat^dag v - omega rhat^dag t
+// (rhat^dag v from the first operator's epilogue, rhat^dag t from the
+// second's), so beta is known before the vector updates and x, r and p are
+// updated in one pass (8 vector passes instead of 11).  The recurrence loses
+// digits as |r| falls, which an inner solve to a few per cent does not feel;
+// the FP64 solver keeps the direct product.
+__device__ __forceinline__ void scalar_omega_beta_body(RhsState *st, const double2 *partials, int G,
+                                                       int N, int r) {
+    const double2 ts = block_sum(partials, 0, G, N, r);
+    const double2 tt = block_sum(partials, 1, G, N, r);
+    const double2 rt = block_sum(partials, 2, G, N, r);
+    if (threadIdx.x == 0) {
+        RhsState s = st[r];
+        if (!s.active) {
+            s.omega = make_double2(0, 0);
+            s.beta = make_double2(0, 0);
+        } else if (!(tt.x > 0.0)) {
+            // t = 0: s is the residual; take x += alpha p and stop
+            s.omega = make_double2(0, 0);
+            s.beta = make_double2(0, 0);
+            s.active = 0;
+            s.flag = 2;
+        } else {
+            s.omega = make_double2(ts.x / tt.x, ts.y / tt.x);
+            const double2 a_rv = cmuld(s.alpha, s.rv), w_rt = cmuld(s.omega, rt);
+            const double2 rho_new = make_double2(s.rho.x - a_rv.x - w_rt.x, s.rho.y - a_rv.y - w_rt.y);
+            if ((rho_new.x == 0.0 && rho_new.y == 0.0) || (s.omega.x == 0.0 && s.omega.y == 0.0)) {
+                s.beta = make_double2(0, 0);
+                s.active = 0;
+                s.flag = 2;
+            } else {
+                s.beta = cmuld(cdiv(rho_new, s.rho), cdiv(s.alpha, s.omega));
+                s.rho = rho_new;
+            }
+        }
+        st[r] = s;
+    }
+}
+
+// After the fused update: ||r||^2, convergence and the iteration count.
+__device__ __forceinline__ void scalar_check_body(RhsState *st, const double2 *partials, int G,
+                                                  int N, int r) {
+    const double2 rr = block_sum(partials, 0, G, N, r);
+    if (threadIdx.x == 0) {
+        RhsState s = st[r];
+        if (s.active || s.flag == 2) {
+            if (s.active) s.iters += 1;
+            s.rr = rr.x;
+            if (s.active && !(rr.x > s.tol2 * s.bb)) {
+                s.active = 0;
+                s.flag = 1;
+            } else if (!isfinite(rr.x)) {
+                s.active = 0;
+                s.flag = 2;
+            }
+        }
+        st[r] = s;
+    }
+}
+
+// x += alpha p + omega s;  r = s - omega t;  p = r + beta (p - omega v);
+// partials: ||r||^2
+template <class S>
+__device__ __forceinline__ void update_xrp_body(const Geom &g, int N, int NT, int SB,
+                                                const RhsState *__restrict__ st, SpinorPtr<S> xv,
+                                                SpinorPtr<S> pv, SpinorPtr<S> sv, SpinorPtr<S> tv,
+                                                SpinorPtr<S> rv, SpinorPtr<S> vv,
+                                                double2 *partials, int tile, int lb, int gb) {
+    using R = Rl<S>;
+    __shared__ double2 red[256];
+    double d0 = 0;
+    SITE_LOOP_BEGIN_AT(tile, lb, gb)
+    const cplx<R> a = to_c<S>(st[r].alpha);
+    const cplx<R> w = to_c<S>(st[r].omega);
+    const cplx<R> b = to_c<S>(st[r].beta);
+    cplx<R> x[12], p[12], sv_[12], t[12], v[12];
+    load_site<S>(xv, s, r, x);
+    load_site<S>(pv, s, r, p);
+    load_site<S>(sv, s, r, sv_);
+    load_site<S>(tv, s, r, t);
+    load_site<S>(vv, s, r, v);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        x[k] = cadd(x[k], cadd(cmul(a, p[k]), cmul(w, sv_[k])));
+        const cplx<R> rn = csub(sv_[k], cmul(w, t[k]));
+        p[k] = cadd(rn, cmul(b, csub(p[k], cmul(w, v[k]))));
+        sv_[k] = rn;
+        d0 += (double)rn.re * rn.re + (double)rn.im * rn.im;
+    }
+    store_site<S>(xv, s, r, x);
+    store_site<S>(rv, s, r, sv_);
+    store_site<S>(pv, s, r, p);
+    SITE_LOOP_END
+    red[tid] = make_double2(d0, 0.0);
+    __syncthreads();
+    if (ry == 0 && r < N) {
+        double2 s0 = red[rl];
+        for (int y = 1; y < SB; ++y) s0.x += red[y * NT + rl].x;
+        partials[(size_t)Lb * N + r] = s0;
+    }
 }
 
 // dst(T) = src(S) converted (and optionally dst += src when ADD)
@@ -466,6 +572,91 @@ __device__ __forceinline__ void hop_pair(const Geom &g, const typename S::link *
     if constexpr (PIN != 0) pin(acc);
 }
 
+// Dot-product partials of the operator epilogues (per thread, then per block)
+struct EpiAcc {
+    double d0r = 0, d0i = 0, d1r = 0, d2r = 0, d2i = 0;
+};
+
+// Reduces the epilogue partials over the block and writes
+// partials[(d * Gb + Lb) * N + r] for the slots the epilogue fills:
+// d = 0 (complex), d = 1 (real part), d = 2 (complex, EPI_DOT_TSR only).
+template <int EPI>
+__device__ __forceinline__ void epi_reduce(double2 (&red)[3][256], int tid, int rl, int ry, int r,
+                                           int N, int NT, int SB, const EpiAcc &e,
+                                           double2 *__restrict__ partials, int Lb, int Gb) {
+    red[0][tid] = make_double2(e.d0r, e.d0i);
+    red[1][tid] = make_double2(e.d1r, 0.0);
+    red[2][tid] = make_double2(e.d2r, e.d2i);
+    __syncthreads();
+    if (ry == 0 && r < N) {
+        double2 s0 = red[0][rl], s1 = red[1][rl], s2 = red[2][rl];
+        for (int y = 1; y < SB; ++y) {
+            const double2 a0 = red[0][y * NT + rl], a1 = red[1][y * NT + rl],
+                          a2 = red[2][y * NT + rl];
+            s0.x += a0.x;
+            s0.y += a0.y;
+            s1.x += a1.x;
+            s2.x += a2.x;
+            s2.y += a2.y;
+        }
+        partials[((size_t)0 * Gb + Lb) * N + r] = s0;
+        if (EPI != EPI_DOT_AUX) partials[((size_t)1 * Gb + Lb) * N + r] = s1;
+        if (EPI == EPI_DOT_TSR) partials[((size_t)2 * Gb + Lb) * N + r] = s2;
+    }
+}
+
+// Output of one site from the hop sum and the (scaled) own spinor, with the
+// epilogue's dot contributions; stores the result.
+//  EPI_DOT_AUX: d0 += aux^dag out
+//  EPI_DOT_TS:  d0 += out^dag in, d1 += ||out||^2
+//  EPI_DOT_TSR: as EPI_DOT_TS, and d2 += aux^dag out
+//  EPI_RESID:   out = aux - D in; d0 += ||out||^2, d1 += ||aux||^2
+template <class S, int NC, int EPI>
+__device__ __forceinline__ void finish_site(typename S::real diag, const cplx<typename S::real> (&c)[12],
+                                            const cplx<typename S::real> (&acc)[12], SpinorPtr<S> out,
+                                            SpinorPtr<S> aux, int s, int r, EpiAcc &e) {
+    using R = typename S::real;
+    cplx<R> o[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        o[k] = {diag * c[k].re - R(0.5) * acc[k].re, diag * c[k].im - R(0.5) * acc[k].im};
+    if constexpr (EPI == EPI_RESID) {
+        cplx<R> b[12];
+        WDT_AUX_LOAD<S, NC>(aux, s, r, b);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            o[k] = csub(b[k], o[k]);
+            e.d0r += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
+            e.d1r += (double)b[k].re * b[k].re + (double)b[k].im * b[k].im;
+        }
+    } else if constexpr (EPI == EPI_DOT_AUX) {
+        cplx<R> a[12];
+        WDT_AUX_LOAD<S, NC>(aux, s, r, a);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            e.d0r += (double)a[k].re * o[k].re + (double)a[k].im * o[k].im;
+            e.d0i += (double)a[k].re * o[k].im - (double)a[k].im * o[k].re;
+        }
+    } else if constexpr (EPI == EPI_DOT_TS || EPI == EPI_DOT_TSR) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            e.d0r += (double)o[k].re * c[k].re + (double)o[k].im * c[k].im;
+            e.d0i += (double)o[k].re * c[k].im - (double)o[k].im * c[k].re;
+            e.d1r += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
+        }
+        if constexpr (EPI == EPI_DOT_TSR) {
+            cplx<R> a[12];
+            WDT_AUX_LOAD<S, NC>(aux, s, r, a);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                e.d2r += (double)a[k].re * o[k].re + (double)a[k].im * o[k].im;
+                e.d2i += (double)a[k].re * o[k].im - (double)a[k].im * o[k].re;
+            }
+        }
+    }
+    store_site<S, WDT_OP_STREAM_STORES != 0, NC>(out, s, r, o);
+}
+
 // WPS (one site per wavefront): NT = 64, the lanes are the RHS of one site,
 // so the site, its neighbours and the link addresses are wave-uniform; the
 // links then come through the scalar cache into SGPRs instead of occupying
@@ -478,7 +669,7 @@ __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::lin
                                             int tile1, int Lb, int Gb) {
     using R = typename S::real;
     constexpr int PIN = OpPin<S>::value;
-    __shared__ double2 red[2][256];
+    __shared__ double2 red[3][256];
     const int tid = threadIdx.x;
     const int rl = WPS ? (tid & 63) : tid % NT;
     const int ry = WPS ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid / NT;
@@ -488,7 +679,7 @@ __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::lin
     for (int tile = tile0; tile < tile1; ++tile) {
     const int r = tile * NT + rl;
     const bool live = (ry < SB) && (r < N);
-    double d0r = 0, d0i = 0, d1r = 0, d1i = 0;
+    EpiAcc e;
     if (live) {
         for (int grp = sw.first; grp < sw.end; grp += sw.step) {
             const int p = grp * SB + ry;
@@ -504,121 +695,14 @@ __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::lin
             hop_pair<3, DAG, PIN, NC, S>(g, U, in, s, nb, r, acc);
             cplx<R> c[12];
             load_site<S, NC>(in, s, r, c);
-            cplx<R> o[12];
-#pragma unroll
-            for (int k = 0; k < 12; ++k)
-                o[k] = {diag * c[k].re - R(0.5) * acc[k].re, diag * c[k].im - R(0.5) * acc[k].im};
-            if constexpr (EPI == EPI_RESID) {
-                cplx<R> b[12];
-                WDT_AUX_LOAD<S, NC>(aux, s, r, b);
-#pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    o[k] = csub(b[k], o[k]);
-                    d0r += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
-                    d1r += (double)b[k].re * b[k].re + (double)b[k].im * b[k].im;
-                }
-            } else if constexpr (EPI == EPI_DOT_AUX) {
-                cplx<R> a[12];
-                WDT_AUX_LOAD<S, NC>(aux, s, r, a);
-#pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    d0r += (double)a[k].re * o[k].re + (double)a[k].im * o[k].im;
-                    d0i += (double)a[k].re * o[k].im - (double)a[k].im * o[k].re;
-                }
-            } else if constexpr (EPI == EPI_DOT_TS) {
-#pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    d0r += (double)o[k].re * c[k].re + (double)o[k].im * c[k].im;
-                    d0i += (double)o[k].re * c[k].im - (double)o[k].im * c[k].re;
-                    d1r += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
-                }
-            }
-            store_site<S, WDT_OP_STREAM_STORES != 0, NC>(out, s, r, o);
+            finish_site<S, NC, EPI>(diag, c, acc, out, aux, s, r, e);
         }
     }
     if constexpr (EPI != EPI_NONE) {
-        red[0][tid] = make_double2(d0r, d0i);
-        red[1][tid] = make_double2(d1r, d1i);
-        __syncthreads();
-        if (ry == 0 && r < N) {
-            double2 s0 = red[0][rl], s1 = red[1][rl];
-            for (int y = 1; y < SB; ++y) {
-                const double2 a0 = red[0][y * NT + rl], a1 = red[1][y * NT + rl];
-                s0.x += a0.x;
-                s0.y += a0.y;
-                s1.x += a1.x;
-                s1.y += a1.y;
-            }
-            partials[((size_t)0 * Gb + Lb) * N + r] = s0;
-            if (EPI != EPI_DOT_AUX) partials[((size_t)1 * Gb + Lb) * N + r] = s1;
-        }
+        epi_reduce<EPI>(red, tid, rl, ry, r, N, NT, SB, e, partials, Lb, Gb);
         if (tile + 1 < tile1) __syncthreads();  // red[] is reused by the next tile
     }
     }
-}
-
-// Per-RHS dot partials of the operator epilogues, reduced over the block and
-// written to partials[(d * Gb + Lb) * N + r] (d = 0, 1).
-template <int EPI>
-__device__ __forceinline__ void epi_reduce(double2 (&red)[2][256], int tid, int rl, int ry, int r,
-                                           int N, int NT, int SB, double d0r, double d0i,
-                                           double d1r, double d1i, double2 *__restrict__ partials,
-                                           int Lb, int Gb) {
-    red[0][tid] = make_double2(d0r, d0i);
-    red[1][tid] = make_double2(d1r, d1i);
-    __syncthreads();
-    if (ry == 0 && r < N) {
-        double2 s0 = red[0][rl], s1 = red[1][rl];
-        for (int y = 1; y < SB; ++y) {
-            const double2 a0 = red[0][y * NT + rl], a1 = red[1][y * NT + rl];
-            s0.x += a0.x;
-            s0.y += a0.y;
-            s1.x += a1.x;
-            s1.y += a1.y;
-        }
-        partials[((size_t)0 * Gb + Lb) * N + r] = s0;
-        if (EPI != EPI_DOT_AUX) partials[((size_t)1 * Gb + Lb) * N + r] = s1;
-    }
-}
-
-// Output of one site from the hop sum and the (scaled) own spinor, with the
-// epilogue's dot contributions; stores the result.
-template <class S, int NC, int EPI>
-__device__ __forceinline__ void finish_site(typename S::real diag, const cplx<typename S::real> (&c)[12],
-                                            const cplx<typename S::real> (&acc)[12], SpinorPtr<S> out,
-                                            SpinorPtr<S> aux, int s, int r, double &d0r,
-                                            double &d0i, double &d1r) {
-    using R = typename S::real;
-    cplx<R> o[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k)
-        o[k] = {diag * c[k].re - R(0.5) * acc[k].re, diag * c[k].im - R(0.5) * acc[k].im};
-    if constexpr (EPI == EPI_RESID) {
-        cplx<R> b[12];
-        WDT_AUX_LOAD<S, NC>(aux, s, r, b);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            o[k] = csub(b[k], o[k]);
-            d0r += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
-            d1r += (double)b[k].re * b[k].re + (double)b[k].im * b[k].im;
-        }
-    } else if constexpr (EPI == EPI_DOT_AUX) {
-        cplx<R> a[12];
-        WDT_AUX_LOAD<S, NC>(aux, s, r, a);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            d0r += (double)a[k].re * o[k].re + (double)a[k].im * o[k].im;
-            d0i += (double)a[k].re * o[k].im - (double)a[k].im * o[k].re;
-        }
-    } else if constexpr (EPI == EPI_DOT_TS) {
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            d0r += (double)o[k].re * c[k].re + (double)o[k].im * c[k].im;
-            d0i += (double)o[k].re * c[k].im - (double)o[k].im * c[k].re;
-            d1r += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
-        }
-    }
-    store_site<S, WDT_OP_STREAM_STORES != 0, NC>(out, s, r, o);
 }
 
 // The same operator with every thread marching along t through one spatial
@@ -646,7 +730,7 @@ __device__ __forceinline__ void dslash_march_body(const Geom &g, const typename 
     using E = typename S::elem;
     constexpr int PIN = OpPin<S>::value;
     constexpr int SF = DAG ? +1 : -1;
-    __shared__ double2 red[2][256];
+    __shared__ double2 red[3][256];
     const int tid = threadIdx.x;
     const int rl = WPS ? (tid & 63) : tid % NT;
     const int ry = WPS ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid / NT;
@@ -659,7 +743,7 @@ __device__ __forceinline__ void dslash_march_body(const Geom &g, const typename 
     const int nbx = L0 / B.x, nby = L1 / B.y, nbz = L2 / B.z;
     const int ncg = upb * nbx * nby * nbz;                // units per chunk
     const Sweep sw = sweep(ncg * (Lt / TC), Lb, Gb);
-    double d0r = 0, d0i = 0, d1r = 0, d1i = 0;
+    EpiAcc e;
     if (live) {
         for (int u = sw.first; u < sw.end; u += sw.step) {
             const int chunk = u / ncg;
@@ -731,7 +815,7 @@ __device__ __forceinline__ void dslash_march_body(const Geom &g, const typename 
 #pragma unroll
                     for (int k = 0; k < 12; ++k) cc[k] = {cc[k].re * sc, cc[k].im * sc};
                 }
-                finish_site<S, NC, EPI>(diag, cc, acc, out, aux, s, r, d0r, d0i, d1r);
+                finish_site<S, NC, EPI>(diag, cc, acc, out, aux, s, r, e);
 #pragma unroll
                 for (int k = 0; k < 12; ++k) ec[k] = en[k];
                 sc = sn;
@@ -739,7 +823,7 @@ __device__ __forceinline__ void dslash_march_body(const Geom &g, const typename 
         }
     }
     if constexpr (EPI != EPI_NONE)
-        epi_reduce<EPI>(red, tid, rl, ry, r, N, NT, CB, d0r, d0i, d1r, d1i, partials, Lb, Gb);
+        epi_reduce<EPI>(red, tid, rl, ry, r, N, NT, CB, e, partials, Lb, Gb);
 }
 
 }  // namespace wdt

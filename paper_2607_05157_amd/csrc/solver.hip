@@ -33,6 +33,12 @@ __global__ void k_scalar_omega(RhsState *st, const double2 *partials, int G, int
 __global__ void k_scalar_beta(RhsState *st, const double2 *partials, int G, int N) {
     scalar_beta_body(st, partials, G, N, blockIdx.x);
 }
+__global__ void k_scalar_omega_beta(RhsState *st, const double2 *partials, int G, int N) {
+    scalar_omega_beta_body(st, partials, G, N, blockIdx.x);
+}
+__global__ void k_scalar_check(RhsState *st, const double2 *partials, int G, int N) {
+    scalar_check_body(st, partials, G, N, blockIdx.x);
+}
 
 #define WDT_BLOCK_CTX blockIdx.y, xcd_block(blockIdx.x, gridDim.x), gridDim.x
 
@@ -55,6 +61,14 @@ __global__ __launch_bounds__(256) void k_update_p(Geom g, int N, int NT, int SB,
                                                   const RhsState *__restrict__ st, SpinorPtr<S> rv,
                                                   SpinorPtr<S> pv, SpinorPtr<S> vv) {
     update_p_body<S>(g, N, NT, SB, st, rv, pv, vv, WDT_BLOCK_CTX);
+}
+template <class S>
+__global__ __launch_bounds__(256) void k_update_xrp(Geom g, int N, int NT, int SB,
+                                                    const RhsState *__restrict__ st, SpinorPtr<S> xv,
+                                                    SpinorPtr<S> pv, SpinorPtr<S> sv,
+                                                    SpinorPtr<S> tv, SpinorPtr<S> rv,
+                                                    SpinorPtr<S> vv, double2 *partials) {
+    update_xrp_body<S>(g, N, NT, SB, st, xv, pv, sv, tv, rv, vv, partials, WDT_BLOCK_CTX);
 }
 template <class SS, class SD, bool ADD>
 __global__ __launch_bounds__(256) void k_convert(Geom g, int N, int NT, int SB,
@@ -315,6 +329,9 @@ int bicgstab_iterate(Bicg &B, int prec, void *x, void *r, void *rhat, void *p, v
     static const char *nm_s[3] = {"axpy_s_fp64", "axpy_s_fp32", "axpy_s_fp16"};
     static const char *nm_xr[3] = {"update_xr_fp64", "update_xr_fp32", "update_xr_fp16"};
     static const char *nm_p[3] = {"update_p_fp64", "update_p_fp32", "update_p_fp16"};
+    static const char *nm_xrp[3] = {"update_xrp_fp64", "update_xrp_fp32", "update_xrp_fp16"};
+    // the inner solves of the mixed solver take the fused end of iteration
+    constexpr bool fused = !std::is_same<S, F64>::value;
     while (it < max_iter) {
         WDT_TRY(launch_dslash(B.g, B.m0, prec, 0, EPI_DOT_AUX, p, v, rhat, N, B.part, sh, B.stream));
         hipLaunchKernelGGL(k_scalar_alpha, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.G, N);
@@ -323,6 +340,32 @@ int bicgstab_iterate(Bicg &B, int prec, void *x, void *r, void *rhat, void *p, v
             hipLaunchKernelGGL((k_update_s<S>), B.grid, dim3(sh.threads), 0, B.stream, B.geo, N, B.NT,
                                sh.SB, B.st, sp<S>(r, V, N), sp<S>(v, V, N),
                                sp<S>(s, V, N));
+        }
+        if constexpr (fused) {
+            WDT_TRY(launch_dslash(B.g, B.m0, prec, 0, EPI_DOT_TSR, s, t, rhat, N, B.part, sh,
+                                  B.stream));
+            hipLaunchKernelGGL(k_scalar_omega_beta, dim3(N), dim3(256), 0, B.stream, B.st, B.part,
+                               sh.G, N);
+            {
+                ProfScope pr(nm_xrp[prec], 8 * vb, B.stream);
+                hipLaunchKernelGGL((k_update_xrp<S>), B.grid, dim3(sh.threads), 0, B.stream, B.geo,
+                                   N, B.NT, sh.SB, B.st, sp<S>(x, V, N), sp<S>(p, V, N),
+                                   sp<S>(s, V, N), sp<S>(t, V, N), sp<S>(r, V, N),
+                                   sp<S>(v, V, N), B.part);
+            }
+            hipLaunchKernelGGL(k_scalar_check, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.Gv,
+                               N);
+            WDT_HIP(hipGetLastError());
+            ++it;
+            if (it % check_every == 0 || it == max_iter) {
+                WDT_HIP(hipMemcpyAsync(host_st.data(), B.st, sizeof(RhsState) * N,
+                                       hipMemcpyDeviceToHost, B.stream));
+                WDT_HIP(hipStreamSynchronize(B.stream));
+                bool any = false;
+                for (int k = 0; k < N; ++k) any = any || host_st[k].active;
+                if (!any) break;
+            }
+            continue;
         }
         WDT_TRY(launch_dslash(B.g, B.m0, prec, 0, EPI_DOT_TS, s, t, nullptr, N, B.part, sh, B.stream));
         hipLaunchKernelGGL(k_scalar_omega, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.G, N);
@@ -365,7 +408,7 @@ static int solve_fp64(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
     const Geom geo = shaped_geom(g->lat, sh);
     const int NT = sh.NT;
     const size_t vb = spinor_bytes(V, N, WDT_FP64);
-    const size_t part_bytes = (size_t)2 * std::max(sh.G, sh.Gv) * N * sizeof(double2);
+    const size_t part_bytes = (size_t)3 * std::max(sh.G, sh.Gv) * N * sizeof(double2);
     const size_t st_bytes = ((sizeof(RhsState) * N + 255) / 256) * 256;
     const size_t part_off = 6 * vb;
     const size_t st_off = part_off + ((part_bytes + 255) / 256) * 256;
@@ -429,7 +472,7 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
     const int NT = sh.NT;
     const size_t vb64 = spinor_bytes(V, N, WDT_FP64);
     const size_t vbl = ((spinor_bytes(V, N, prec) + 255) / 256) * 256;
-    const size_t part_bytes = (size_t)2 * std::max(sh.G, sh.Gv) * N * sizeof(double2);
+    const size_t part_bytes = (size_t)3 * std::max(sh.G, sh.Gv) * N * sizeof(double2);
     const size_t st_bytes = ((sizeof(RhsState) * N + 255) / 256) * 256;
     const size_t low_off = vb64;
     const size_t part_off = low_off + 7 * vbl;
