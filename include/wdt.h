@@ -155,7 +155,8 @@ int wdt_apply_D(wdt_gauge g, double m0, const void *dev_in, void *dev_out,
  * Every RHS stops when its true FP64 relative residual ||b - D x|| / ||b||
  * is <= tol.  dev_b, dev_x: FP64 batches; x starts from 0 unless
  * x0_is_guess.  stats (host, may be NULL): n_rhs records.
- * Returns WDT_WNOTCONVERGED if some RHS did not reach tol in max_iter.
+ * Returns WDT_WNOTCONVERGED if some RHS did not reach tol in max_iter, or if
+ * its true residual is not finite (an input holding inf or NaN).
  */
 typedef struct {
     double tol;          /* target true relative residual, e.g. 1e-10 */

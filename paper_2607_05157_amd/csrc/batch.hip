@@ -487,11 +487,11 @@ int wdt_batch_solve(wdt_batch b, void *const *dev_b, void *const *dev_x,
                 if (stats) {
                     stats[k].iterations = total_it[k];
                     stats[k].outer = 0;
-                    stats[k].converged = hs[k].active ? 0 : 1;
+                    stats[k].converged = (!hs[k].active && hs[k].flag == 1) ? 1 : 0;
                     stats[k].restarts = restarts[k];
                     stats[k].true_residual = hs[k].bb > 0 ? std::sqrt(hs[k].rr / hs[k].bb) : 0.0;
                 }
-                if (hs[k].active) rc = WDT_WNOTCONVERGED;
+                if (hs[k].active || hs[k].flag != 1) rc = WDT_WNOTCONVERGED;
             }
             break;
         }

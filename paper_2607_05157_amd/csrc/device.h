@@ -273,6 +273,9 @@ __device__ __forceinline__ void store_site(const SpinorPtr<S> &sp, int site, int
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
+        // a site-RHS whose largest part is below the FP32 normal range is
+        // stored as zero (its reciprocal would overflow)
+        if (!(m >= 1.17549435e-38f)) m = 0.f;
         const float inv = (m > 0.f) ? 1.0f / m : 0.f;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {

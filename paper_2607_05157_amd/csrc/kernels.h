@@ -63,9 +63,10 @@ __device__ __forceinline__ void init_state_body(RhsState *st, const double2 *par
         s.omega = make_double2(0, 0);
         s.beta = make_double2(0, 0);
         const bool want = (mask == nullptr) || mask[r];
-        const bool done = !(rr.x > s.tol2 * bb.x);
-        s.active = (want && !done) ? 1 : 0;
-        s.flag = done ? 1 : 0;
+        const bool finite = isfinite(rr.x) && isfinite(bb.x);
+        const bool done = finite && !(rr.x > s.tol2 * bb.x);
+        s.active = (want && finite && !done) ? 1 : 0;
+        s.flag = !finite ? 2 : done ? 1 : 0;
         st[r] = s;
     }
 }
@@ -334,12 +335,17 @@ __device__ __forceinline__ void update_xrp_body(const Geom &g, int N, int NT, in
     }
 }
 
-// dst(T) = src(S) converted (and optionally dst += src when ADD)
+// dst = f[r] * src converted (dst += f[r] * src when ADD); f = nullptr: 1.
+// The product is formed in FP64 before the conversion, so a residual can be
+// brought to unit norm on its way into low precision and the correction
+// scaled back on its way out.
 template <class SS, class SD, bool ADD>
 __device__ __forceinline__ void convert_body(const Geom &g, int N, int NT, int SB,
-                                             SpinorPtr<SS> src, SpinorPtr<SD> dst, int tile,
-                                             int lb, int gb) {
+                                             SpinorPtr<SS> src, SpinorPtr<SD> dst,
+                                             const double *__restrict__ f, int tile, int lb,
+                                             int gb) {
     SITE_LOOP_BEGIN_AT(tile, lb, gb)
+    const double fr = f ? f[r] : 1.0;
     cplx<Rl<SS>> a[12];
     load_site<SS>(src, s, r, a);
     cplx<Rl<SD>> b[12];
@@ -347,12 +353,13 @@ __device__ __forceinline__ void convert_body(const Geom &g, int N, int NT, int S
         load_site<SD>(dst, s, r, b);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            b[k].re += (Rl<SD>)a[k].re;
-            b[k].im += (Rl<SD>)a[k].im;
+            b[k].re += (Rl<SD>)(fr * (double)a[k].re);
+            b[k].im += (Rl<SD>)(fr * (double)a[k].im);
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) b[k] = {(Rl<SD>)a[k].re, (Rl<SD>)a[k].im};
+        for (int k = 0; k < 12; ++k)
+            b[k] = {(Rl<SD>)(fr * (double)a[k].re), (Rl<SD>)(fr * (double)a[k].im)};
     }
     store_site<SD>(dst, s, r, b);
     SITE_LOOP_END

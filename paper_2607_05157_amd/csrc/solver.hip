@@ -72,8 +72,9 @@ __global__ __launch_bounds__(256) void k_update_xrp(Geom g, int N, int NT, int S
 }
 template <class SS, class SD, bool ADD>
 __global__ __launch_bounds__(256) void k_convert(Geom g, int N, int NT, int SB,
-                                                 SpinorPtr<SS> src, SpinorPtr<SD> dst) {
-    convert_body<SS, SD, ADD>(g, N, NT, SB, src, dst, WDT_BLOCK_CTX);
+                                                 SpinorPtr<SS> src, SpinorPtr<SD> dst,
+                                                 const double *__restrict__ f) {
+    convert_body<SS, SD, ADD>(g, N, NT, SB, src, dst, f, WDT_BLOCK_CTX);
 }
 
 // ---------------------------------------------------------------------------
@@ -440,11 +441,11 @@ static int solve_fp64(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
                 if (stats) {
                     stats[k].iterations = total_it[k];
                     stats[k].outer = 0;
-                    stats[k].converged = hs[k].active ? 0 : 1;
+                    stats[k].converged = (!hs[k].active && hs[k].flag == 1) ? 1 : 0;
                     stats[k].restarts = restarts[k];
                     stats[k].true_residual = hs[k].bb > 0 ? std::sqrt(hs[k].rr / hs[k].bb) : 0.0;
                 }
-                if (hs[k].active) rc = WDT_WNOTCONVERGED;
+                if (hs[k].active || hs[k].flag != 1) rc = WDT_WNOTCONVERGED;
             }
             return rc;
         }
@@ -478,13 +479,18 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
     const size_t part_off = low_off + 7 * vbl;
     const size_t st_off = part_off + ((part_bytes + 255) / 256) * 256;
     const size_t mask_off = st_off + st_bytes;
-    WDT_TRY(ensure_ws(g, mask_off + ((sizeof(int) * N + 255) / 256) * 256));
+    const size_t fac_off = mask_off + ((sizeof(int) * N + 255) / 256) * 256;
+    WDT_TRY(ensure_ws(g, fac_off + 2 * ((sizeof(double) * N + 255) / 256) * 256));
     char *base = (char *)g->ws.ptr;
     void *r64 = base;
     void *lo[7];
     for (int i = 0; i < 7; ++i) lo[i] = base + low_off + i * vbl;
     void *rS = lo[0], *rhat = lo[1], *p = lo[2], *v = lo[3], *s = lo[4], *t = lo[5], *e = lo[6];
     int *mask = (int *)(base + mask_off);
+    // per RHS: 1/||r|| into the inner solve, ||r|| back out
+    double *fin = (double *)(base + fac_off);
+    double *fout = fin + ((N + 31) / 32) * 32;
+    std::vector<double> hfac(2 * (size_t)((N + 31) / 32) * 32, 0.0);
     Bicg B{g, m0, N, V, sh, geo, NT, dim3(sh.Gv, sh.tiles), stream,
            (RhsState *)(base + st_off), (double2 *)(base + part_off)};
     const dim3 grid(sh.Gv, sh.tiles);
@@ -515,19 +521,31 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
                 if (stats) {
                     stats[k].iterations = total_it[k];
                     stats[k].outer = outer[k];
-                    stats[k].converged = hs[k].active ? 0 : 1;
+                    stats[k].converged = (!hs[k].active && hs[k].flag == 1) ? 1 : 0;
                     stats[k].restarts = 0;
                     stats[k].true_residual = hs[k].bb > 0 ? std::sqrt(hs[k].rr / hs[k].bb) : 0.0;
                 }
-                if (hs[k].active) rc = WDT_WNOTCONVERGED;
+                if (hs[k].active || hs[k].flag != 1) rc = WDT_WNOTCONVERGED;
             }
             return rc;
         }
         for (int k = 0; k < N; ++k) outer[k] += hmask[k];
         WDT_HIP(hipMemcpyAsync(mask, hmask.data(), sizeof(int) * N, hipMemcpyHostToDevice, stream));
+        // The inner system is D e = r / ||r|| (unit norm whatever the scale of
+        // b, so the low-precision data stays far from under- and overflow as
+        // the residual falls); x += ||r|| e afterwards.
+        const size_t half = hfac.size() / 2;
+        for (int k = 0; k < N; ++k) {
+            const double nr = std::sqrt(hs[k].rr);
+            const bool ok = hmask[k] && nr > 0 && std::isfinite(nr);
+            hfac[k] = ok ? 1.0 / nr : 0.0;
+            hfac[half + k] = ok ? nr : 0.0;
+        }
+        WDT_HIP(hipMemcpyAsync(fin, hfac.data(), sizeof(double) * hfac.size(), hipMemcpyHostToDevice,
+                               stream));
         // inner system D e = r (low precision), e = 0, rhat = r
         hipLaunchKernelGGL((k_convert<F64, S, false>), grid, dim3(sh.threads), 0, stream, geo, N, NT,
-                           sh.SB, sp<F64>(r64, V, N), sp<S>(rS, V, N));
+                           sh.SB, sp<F64>(r64, V, N), sp<S>(rS, V, N), (const double *)fin);
         WDT_HIP(hipMemsetAsync(e, 0, vbl, stream));
         // ||r||^2 in the stored precision: residual of e = 0 against rS
         WDT_TRY(launch_dslash(g, m0, prec, 0, EPI_RESID, e, rhat, rS, N, B.part, sh, stream));
@@ -546,7 +564,7 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
         budget -= done;
         // x += e
         hipLaunchKernelGGL((k_convert<S, F64, true>), grid, dim3(sh.threads), 0, stream, geo, N, NT,
-                           sh.SB, sp<S>(e, V, N), sp<F64>(x, V, N));
+                           sh.SB, sp<S>(e, V, N), sp<F64>(x, V, N), (const double *)fout);
         WDT_HIP(hipGetLastError());
     }
     (void)rc;

@@ -465,3 +465,52 @@ def test_apply_D_24c48_64rhs_sampled():
     scale = w.index_select(0, sc).cpu().numpy().view(np.float32).reshape(len(sites), 1, N)
     goth = (halves[..., 0].astype(np.float64) + 1j * halves[..., 1].astype(np.float64)) * scale
     assert np.max(np.abs(goth - ref)) < 4e-3 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_solve_zero_and_scaled_rhs(c1, prec):
+    """Degenerate right-hand sides in one batch: b = 0 must give x = 0 with no
+    iterations; b scaled by 1e-30 and 1e+30 must solve like b itself (the
+    tolerance is relative; FP16 storage scales per site and RHS)."""
+    say("solve degenerate rhs", prec)
+    dims, m0, U, Dinv = c1
+    N = 6
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    b = lat.new_batch(N)
+    W.sources(lat, W.source_descs([40, 41, 42, 43, 44, 45]), b)
+    b[:, :, 1] = 0
+    b[:, :, 3] = 0
+    b[:, :, 4] *= 1e-30
+    b[:, :, 5] *= 1e30
+    x = lat.new_batch(N)
+    p = W.FP64 if prec == "fp64" else W.FP16
+    rc, st = W.solve(g, m0, b, x, N, tol=1e-10, prec=p)
+    assert rc == W.OK
+    xs = x.cpu().numpy().reshape(-1, N)
+    assert np.all(xs[:, 1] == 0) and np.all(xs[:, 3] == 0)
+    assert st[1]["iterations"] == 0 and st[3]["iterations"] == 0
+    X = Dinv @ b.cpu().numpy().reshape(-1, N)
+    for k in (0, 2, 4, 5):
+        assert np.linalg.norm(xs[:, k] - X[:, k]) <= 1e-8 * np.linalg.norm(X[:, k]), k
+
+
+@pytest.mark.parametrize("N", [65, 128])
+def test_apply_D_batch_sizes_beyond_constants(N):
+    """Batch sizes that use neither a compiled-in constant nor one site per
+    wavefront (several RHS tiles, ragged last tile)."""
+    dims = (4, 2, 4, 6)
+    say("apply_D", N)
+    V = int(np.prod(dims))
+    U = gauge_field(dims, 0.5, seed=23)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    psi = rand_batch(V, N, 9)
+    ref = dirac.apply_D(U, 0.3, psi, dims, -1)
+    out = lat.new_batch(N)
+    W.apply_D(g, 0.3, to_dev(psi), out, N, W.FP64)
+    assert np.max(np.abs(out.cpu().numpy() - ref)) < 1e-14 * np.max(np.abs(ref))
+    x = fp16_batch(psi)
+    oh = torch.zeros_like(x)
+    W.apply_D(g, 0.3, x, oh, N, W.FP16)
+    assert np.max(np.abs(from_fp16(oh, V, N) - ref)) < 4e-3 * np.max(np.abs(ref))
