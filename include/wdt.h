@@ -31,7 +31,10 @@
  * Host links: double [V][4][3][3][2] = U_mu(x)[a][b] (re, im).
  * Streams.  `stream` is a hipStream_t (NULL = default stream).  Calls are
  *   asynchronous on that stream unless they return host data, in which case
- *   they synchronise the stream before returning.
+ *   they synchronise the stream before returning.  wdt_solve keeps its
+ *   workspace with the gauge handle: solves with one gauge on different
+ *   streams must be ordered by the caller (one stream per gauge handle, or
+ *   an event between them).
  * Errors.  Every function returns an int: 0 success, > 0 a warning with
  *   results written, < 0 an error (no output written or output undefined).
  *   wdt_error_string maps a code to text; wdt_last_error_detail gives the

@@ -514,3 +514,62 @@ def test_apply_D_batch_sizes_beyond_constants(N):
     oh = torch.zeros_like(x)
     W.apply_D(g, 0.3, x, oh, N, W.FP16)
     assert np.max(np.abs(from_fp16(oh, V, N) - ref)) < 4e-3 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (3, 5, 2, 3), (2, 3, 4, 5)])
+@pytest.mark.parametrize("N", [1, 48])
+def test_small_and_odd_lattices(dims, N):
+    """Extent 2 (forward and backward neighbour coincide), odd extents (no
+    brick divides them), against the oracle: operator in FP64 and FP16, and a
+    mixed solve against dense LU."""
+    say("small/odd lattice", dims, N)
+    V = int(np.prod(dims))
+    U = gauge_field(dims, 0.4, seed=31)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    psi = rand_batch(V, N, 12)
+    for dagger in (False, True):
+        ref = dirac.apply_D(U, 0.25, psi, dims, -1, dagger=dagger)
+        out = lat.new_batch(N)
+        W.apply_D(g, 0.25, to_dev(psi), out, N, W.FP64, dagger)
+        assert np.max(np.abs(out.cpu().numpy() - ref)) < 1e-14 * np.max(np.abs(ref))
+    ref = dirac.apply_D(U, 0.25, psi, dims, -1)
+    x = fp16_batch(psi)
+    oh = torch.zeros_like(x)
+    W.apply_D(g, 0.25, x, oh, N, W.FP16)
+    assert np.max(np.abs(from_fp16(oh, V, N) - ref)) < 4e-3 * np.max(np.abs(ref))
+    b = lat.new_batch(N)
+    W.sources(lat, W.source_descs(list(range(90, 90 + N))), b)
+    xs = lat.new_batch(N)
+    rc, st = W.solve(g, 0.25, b, xs, N, tol=1e-11, prec=W.FP16)
+    assert rc == W.OK
+    X = osolve.dense_solve(dirac.dense_D(U, 0.25, dims, -1), b.cpu().numpy().reshape(-1, N))
+    got = xs.cpu().numpy().reshape(-1, N)
+    assert np.max(np.linalg.norm(got - X, axis=0) / np.linalg.norm(X, axis=0)) < 1e-9
+
+
+def test_side_stream_matches_default_stream(c1):
+    """Sources, an FP64 solve and the contraction issued on a non-default
+    torch stream give bit-identical results to the default stream."""
+    say("side stream")
+    dims, m0, U, Dinv = c1
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    N = 8
+
+    def run():
+        b = lat.new_batch(N)
+        W.sources(lat, W.source_descs(list(range(300, 300 + N))), b)
+        x = lat.new_batch(N)
+        W.solve(g, m0, b, x, N, tol=1e-12)
+        loop = W.contract(lat, b, x, N, spin=gamma.GAMMA5)
+        return x, loop
+
+    x0, l0 = run()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        x1, l1 = run()
+    side.synchronize()
+    assert torch.equal(x0, x1)
+    assert np.array_equal(l0, l1)
