@@ -54,6 +54,24 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def stream_copy_gbps(nbytes, reps=10):
+    """Device-to-device copy of nbytes (read + write counted): what a plain
+    streaming kernel reaches on this GPU."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2 * a.numel() * 4 / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+
+
 def cpu_baseline(U, m0, dims, b_host, n_rhs):
     """The oracle's operator (scipy CSR assembled from the definition, then a
     sparse product) applied to the whole batch, timed on this host."""
@@ -123,7 +141,7 @@ def batched_leg(log, n_per_shape=32):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
@@ -181,8 +199,11 @@ def main():
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     stats = []
+    step_ms = []
     for k in range(args.steps):
-        st, loop = step(present[k % len(present)], wdt.FP16)
+        ts = time.perf_counter()
+        st, loop = step(present[k % len(present)], wdt.FP16)   # ends with a host read-back
+        step_ms.append((time.perf_counter() - ts) * 1e3)
         stats.append(st)
     torch.cuda.synchronize()
     t_mixed = (time.perf_counter() - t_start) / args.steps
@@ -218,6 +239,7 @@ def main():
     iters = [s["iterations"] for st in stats for s in st]
     outer = [s["outer"] for st in stats for s in st]
 
+    stream = stream_copy_gbps(b.numel() * b.element_size())
     batched = None
     if not args.no_batched:
         batched = batched_leg(log)
@@ -246,6 +268,10 @@ def main():
                    "sigma": list(sigma), "colour_batches_per_trace": len(present),
                    "tol": cfg["tol"], "inner_tol": args.inner_tol},
         "pct_of_hbm_peak": round(100 * value / HBM_PEAK_GBPS, 1),
+        "stream_copy_gbps": round(stream, 1),
+        "pct_of_stream": round(100 * value / stream, 1),
+        "step_ms": [round(v, 2) for v in step_ms],
+        "median_step_ms": round(sorted(step_ms)[len(step_ms) // 2], 3),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "bytes_per_launch": per_launch_b, "avg_launch_ms": per_launch_ms,
