@@ -1,0 +1,109 @@
+"""Probing-variance study: how the variance of the disconnected-loop estimate
+tr[gamma5 D^-1(t0, t0)] falls with the distance of the torus colouring, and
+what that means for the number of solves needed to reach a target error
+(Sec. 3: probing with the colouring of eq. coloring-formula, time dilution,
+spin-colour dilution; Sec. 4 and Fig. 3: total solves against the target
+accuracy).
+
+Each row is one estimator:
+  hutchinson  eta restricted to t0, one solve per sample;
+  dil12       eta restricted to t0, one solve per spin-colour component;
+  probe dD    colours of a distance-D torus colouring (of the time slice,
+              dim=3, or of the whole lattice, dim=4) present on t0, times
+              spin-colour dilution: (colours on t0) x 12 solves per sample.
+For each: the mean over seeds, the seed-to-seed sample variance (complex,
+N - 1), the solves one sample costs, their product (solves per unit of
+inverse variance: the figure of merit) and N_total = solves per sample x
+ceil(variance / eps^2), the solves needed for a standard error eps.
+
+    python -m paper_2607_05157_amd.study --dims 16 16 16 32 --m0 0.02 --eps 0.5 \\
+        --seeds 8 --distances 1 2 3 4 --out study.json
+
+Everything runs through the library (sources, solves, contractions); this
+module only chooses colourings and adds up the results.
+"""
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+if __name__ == "__main__":
+    import os
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+from paper_2607_05157_amd import estimator, wdt  # noqa: E402
+
+
+def colouring(dims, d, dim):
+    """(n_c, sigma[4]) of the distance-d colouring of the time slice (dim=3,
+    sigma_t = 0) or of the whole lattice (dim=4)."""
+    if dim == 3:
+        n_c, s = wdt.colouring_search(tuple(dims[:3]), d)
+        return n_c, tuple(s) + (0,)
+    n_c, s = wdt.colouring_search(tuple(dims), d)
+    return n_c, tuple(s)
+
+
+def run(gauge, lat, m0, t0, seeds, distances=(1, 2, 3, 4), dim=3, eps=None, n_rhs=48,
+        prec=wdt.FP16, tol=1e-10, baselines=True, log=None):
+    rows = []
+    specs = []
+    if baselines:
+        specs.append(("hutchinson", 0, 1, (0, 0, 0, 0), 1))
+        specs.append(("dil12", 0, 1, (0, 0, 0, 0), 12))
+    for d in distances:
+        n_c, sigma = colouring(lat.dims, d, dim)
+        specs.append((f"probe d{d}", d, n_c, sigma, 12))
+    for name, d, n_c, sigma, dil in specs:
+        t = time.perf_counter()
+        out = estimator.probing_loop(gauge, lat, m0, n_c, sigma, t0, list(seeds), n_rhs=n_rhs,
+                                     dilution=dil, tol=tol, prec=prec)
+        dt = time.perf_counter() - t
+        solves = len(out["colours"]) * (12 if dil == 12 else 1)
+        var = out["var_seeds"]
+        row = dict(estimator=name, distance=d, n_c=n_c, sigma=list(sigma),
+                   colours_on_slice=len(out["colours"]), solves_per_sample=solves,
+                   estimate=[out["estimate"].real, out["estimate"].imag], variance=var,
+                   std_error=math.sqrt(var / len(seeds)), seeds=len(seeds), seconds=round(dt, 3),
+                   cost=solves * var,
+                   per_seed_re=out["per_seed"].real.tolist(),
+                   per_seed_im=out["per_seed"].imag.tolist())
+        if eps:
+            row["n_total"] = solves * max(1, math.ceil(var / eps ** 2))
+        rows.append(row)
+        if log:
+            log(json.dumps({k: v for k, v in row.items() if not k.startswith("per_seed")}))
+    return rows
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--dims", type=int, nargs=4, default=[16, 16, 16, 32])
+    ap.add_argument("--eps-link", type=float, default=0.5, help="link spread of the gauge field")
+    ap.add_argument("--gauge-seed", type=int, default=2)
+    ap.add_argument("--m0", type=float, default=0.02)
+    ap.add_argument("--t0", type=int, default=0)
+    ap.add_argument("--seeds", type=int, default=8)
+    ap.add_argument("--distances", type=int, nargs="+", default=[1, 2, 3, 4])
+    ap.add_argument("--dim", type=int, default=3, choices=[3, 4])
+    ap.add_argument("--eps", type=float, default=None, help="target standard error for N_total")
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    from synth.gauge import gauge_field
+    wdt.init(0)
+    dims = tuple(a.dims)
+    lat = wdt.Lattice(dims, -1)
+    g = wdt.Gauge(lat, gauge_field(dims, a.eps_link, a.gauge_seed))
+    rows = run(g, lat, a.m0, a.t0, range(a.seeds), a.distances, a.dim, a.eps,
+               log=lambda s: print(s, flush=True))
+    if a.out:
+        json.dump(dict(dims=list(dims), m0=a.m0, eps_link=a.eps_link, rows=rows), open(a.out, "w"),
+                  indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

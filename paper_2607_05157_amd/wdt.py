@@ -55,6 +55,11 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} not found: build it with "
                                "`python -m paper_2607_05157_amd.build` (no CPU fallback exists)")
+        # PyTorch first: the library's HIP runtime dependency (same soname)
+        # then resolves to the runtime torch has loaded, so the process has
+        # one runtime; loaded the other way round, two runtimes coexist and
+        # torch sees no GPU.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         P = ctypes.POINTER

@@ -10,6 +10,7 @@ import pytest
 from paper_2607_05157_amd import wdt
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_library_exports_every_header_function():
@@ -85,3 +86,15 @@ def test_colouring_check_and_search_failure():
     with pytest.raises(wdt.WdtError) as e:
         wdt.colouring_search((8, 8, 8, 8), 3, max_nc=8)
     assert e.value.code == wdt.ESEARCH
+
+
+def test_library_shares_torchs_hip_runtime():
+    """Loading the library through the binding, in a fresh process that has
+    not imported torch, leaves exactly one HIP runtime in the process."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r); from paper_2607_05157_amd import wdt; wdt.lib(); "
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().splitlines()[-1] == "1"

@@ -174,3 +174,47 @@ def test_traceloss_finite_differences_8x4():
             # d Re(sum f) / d Re U = Re(grad), d / d Im U = Im(grad) (torch convention)
             want = gU[s, mu, a, b].real if unit == 1.0 else gU[s, mu, a, b].imag
             assert abs(fd.real - want) < 2e-5 * max(abs(want), 1e-2), (s, mu, a, b, unit, fd, want)
+
+
+def test_variance_study_matches_oracle():
+    """The probing-variance study on 4^4 in FP64: every estimator's per-seed
+    values against the oracle's dense-inverse estimates with the same noise,
+    the 3D slice colourings against the oracle's own search, and the
+    variance and N_total bookkeeping."""
+    from paper_2607_05157_amd import study
+    dims, m0, t0, seeds = (4, 4, 4, 4), 0.2, 2, [0, 1, 2, 3, 4]
+    say("variance study", dims)
+    U = gauge_field(dims, 0.3, seed=1)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    rows = study.run(g, lat, m0, t0, seeds, distances=(1, 2), dim=3, eps=0.5, prec=W.FP64,
+                     tol=1e-12)
+    V = int(np.prod(dims))
+    Dinv = osolve.dense_inverse(dirac.dense_D(U, m0, dims, -1))
+    for row in rows:
+        if row["distance"] == 0:
+            col, nc, comps = None, 1, ([-1] if row["estimator"] == "hutchinson" else list(range(12)))
+            classes = [0]
+        else:
+            nc, sig3 = colouring.search(dims[:3], row["distance"])
+            assert (nc, list(sig3) + [0]) == (row["n_c"], row["sigma"])
+            col = colouring.colours(dims, row["sigma"], nc)
+            comps = list(range(12))
+            classes = sorted(set(col[np.arange(V) // 64 == t0].tolist()))
+        ref = []
+        for s in seeds:
+            tot = 0j
+            for j in classes:
+                for k in comps:
+                    v = noise.probing_vector(dims, s, col, j, k, t0)
+                    if not v.any():
+                        continue
+                    x = (Dinv @ v.ravel()).reshape(V, 12)
+                    tot += oest.sample_dot(v, x, dims, t0, gamma.GAMMA5)
+            ref.append(tot)
+        ref = np.array(ref)
+        got = np.array(row["per_seed_re"]) + 1j * np.array(row["per_seed_im"])
+        assert np.max(np.abs(got - ref)) < 1e-10 * max(1.0, np.max(np.abs(ref))), row["estimator"]
+        assert abs(row["variance"] - oest.sample_variance(ref)) <= 1e-9 * max(1.0, row["variance"])
+        assert row["solves_per_sample"] == len(classes) * len(comps)
+        assert row["n_total"] == row["solves_per_sample"] * max(1, int(np.ceil(row["variance"] / 0.25)))
