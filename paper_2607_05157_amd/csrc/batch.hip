@@ -159,6 +159,35 @@ struct wdt_batch_s {
 
 namespace {
 
+// Destroys an event on every path out of a scope.
+struct EventGuard {
+    hipEvent_t e = nullptr;
+    ~EventGuard() {
+        if (e) (void)hipEventDestroy(e);
+    }
+};
+
+// Orders the batch's stream after the caller's stream on entry and the
+// caller's stream after the batch's on every path out, errors included, so
+// the caller never runs ahead of kernels the batch still has in flight.
+struct StreamJoin {
+    hipStream_t caller, own;
+    hipEvent_t ev = nullptr;
+    int rc = WDT_OK;
+    StreamJoin(hipStream_t c, hipStream_t o) : caller(c), own(o) {
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(ev, caller) != hipSuccess || hipStreamWaitEvent(own, ev, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = set_error(WDT_EHIP, "batch: stream ordering failed");
+        }
+    }
+    ~StreamJoin() {
+        if (!ev) return;
+        if (hipEventRecord(ev, own) == hipSuccess) (void)hipStreamWaitEvent(caller, ev, 0);
+        (void)hipEventDestroy(ev);
+    }
+};
+
 int free_plan(wdt_batch_s *b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -380,9 +409,10 @@ int wdt_batch_tune(wdt_batch b, int32_t iters, double *best_ms) {
     const int tiles[] = {8, 16, 48};
     double best = 1e300;
     int bb = b->blocks_per_cu, bt = b->tile_cap;
-    hipEvent_t e0, e1;
-    WDT_HIP(hipEventCreate(&e0));
-    WDT_HIP(hipEventCreate(&e1));
+    EventGuard g0, g1;
+    WDT_HIP(hipEventCreate(&g0.e));
+    WDT_HIP(hipEventCreate(&g1.e));
+    hipEvent_t e0 = g0.e, e1 = g1.e;
     for (int bpc : bpcs)
         for (int tc : tiles) {
             b->blocks_per_cu = bpc;
@@ -412,8 +442,6 @@ int wdt_batch_tune(wdt_batch b, int32_t iters, double *best_ms) {
                 bt = tc;
             }
         }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     b->blocks_per_cu = bb;
     b->tile_cap = bt;
     WDT_TRY(make_plan(b));
@@ -431,11 +459,9 @@ int wdt_batch_solve(wdt_batch b, void *const *dev_b, void *const *dev_x,
         b->host[i].vec[V_B] = (double2 *)dev_b[i];
         b->host[i].vec[V_X] = (double2 *)dev_x[i];
     }
-    // order the batch stream after the caller's stream, and back at the end
-    hipEvent_t ev;
-    WDT_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    WDT_HIP(hipEventRecord(ev, (hipStream_t)stream));
-    WDT_HIP(hipStreamWaitEvent(b->stream, ev, 0));
+    // the batch stream runs after the caller's stream, and the caller's after it
+    StreamJoin join((hipStream_t)stream, b->stream);
+    if (join.rc < 0) return join.rc;
     assign_blocks(b, std::vector<char>(b->nsys, 1));
     WDT_TRY(upload(b));
     if (!P->x0_is_guess)
@@ -519,9 +545,6 @@ int wdt_batch_solve(wdt_batch b, void *const *dev_b, void *const *dev_x,
         for (int k = 0; k < b->total_rhs; ++k) total_it[k] += hs[k].iters - before[k];
         budget -= it;
     }
-    WDT_HIP(hipEventRecord(ev, b->stream));
-    WDT_HIP(hipStreamWaitEvent((hipStream_t)stream, ev, 0));
-    WDT_HIP(hipEventDestroy(ev));
     return rc;
 }
 

@@ -209,13 +209,12 @@ static int contract(const wdt_lattice_s *lat, const void *src, const void *sol, 
     for (int i = 0; i < 16; ++i)
         Bm.m[i] = B ? make_double2(B[2 * i], B[2 * i + 1])
                     : make_double2((i % 5 == 0) ? 1.0 : 0.0, 0.0);
-    double2 *buf = nullptr;
     const size_t pbytes = (size_t)Lt * nb * N * sizeof(double2);
     const size_t obytes = (size_t)N * Lt * sizeof(double2);
-    if (hipMallocAsync((void **)&buf, pbytes + obytes, stream) != hipSuccess) {
-        (void)hipGetLastError();
+    AsyncScratch scratch(stream);
+    if (!scratch.alloc(pbytes + obytes))
         return set_error(WDT_ENOMEM, "contract: scratch allocation failed");
-    }
+    double2 *buf = (double2 *)scratch.p;
     const dim3 grid(nb, Lt, sh.tiles);
     SpinorPtr<F64> ps = make_spinor<F64>(const_cast<void *>(src), g.V, N);
     SpinorPtr<F64> px = make_spinor<F64>(const_cast<void *>(sol), g.V, N);
@@ -231,7 +230,6 @@ static int contract(const wdt_lattice_s *lat, const void *src, const void *sol, 
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(host_out, outd, obytes, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    (void)hipFreeAsync(buf, stream);
     if (e != hipSuccess) return set_error(WDT_EHIP, "contract: %s", hipGetErrorString(e));
     return WDT_OK;
 }
@@ -381,11 +379,10 @@ int wdt_sources(wdt_lattice lat, const wdt_source_desc *desc, int32_t n_rhs, voi
         WDT_CHECK(desc[r].t0 < lat->dims[3], "wdt_sources: t0 out of range");
     }
     const hipStream_t st = (hipStream_t)stream;
-    wdt_source_desc *dd = nullptr;
-    if (hipMallocAsync((void **)&dd, sizeof(wdt_source_desc) * n_rhs, st) != hipSuccess) {
-        (void)hipGetLastError();
+    AsyncScratch scratch(st);
+    if (!scratch.alloc(sizeof(wdt_source_desc) * n_rhs))
         return set_error(WDT_ENOMEM, "wdt_sources: scratch allocation failed");
-    }
+    wdt_source_desc *dd = (wdt_source_desc *)scratch.p;
     WDT_HIP(hipMemcpyAsync(dd, desc, sizeof(wdt_source_desc) * n_rhs, hipMemcpyHostToDevice, st));
     const Shape sh = site_shape(*lat, n_rhs, prec);
     const Geom g = shaped_geom(*lat, sh);
@@ -406,7 +403,6 @@ int wdt_sources(wdt_lattice lat, const wdt_source_desc *desc, int32_t n_rhs, voi
             break;
     }
     WDT_HIP(hipGetLastError());
-    WDT_HIP(hipFreeAsync(dd, st));
     return WDT_OK;
 }
 
@@ -431,18 +427,16 @@ int wdt_force(wdt_gauge g, const void *dev_x, const void *dev_y, int32_t n_rhs,
               "wdt_force: bad argument");
     const hipStream_t st = (hipStream_t)stream;
     const Geom geo = g->lat.geom();
-    double2 *dg = nullptr;
-    if (hipMallocAsync((void **)&dg, sizeof(double2) * n_rhs, st) != hipSuccess) {
-        (void)hipGetLastError();
+    AsyncScratch scratch(st);
+    if (!scratch.alloc(sizeof(double2) * n_rhs))
         return set_error(WDT_ENOMEM, "wdt_force: scratch allocation failed");
-    }
+    double2 *dg = (double2 *)scratch.p;
     WDT_HIP(hipMemcpyAsync(dg, grad_out, sizeof(double2) * n_rhs, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_force, dim3((geo.V * 4 + 255) / 256), dim3(256), 0, st, geo,
                        make_spinor<F64>(const_cast<void *>(dev_x), geo.V, n_rhs),
                        make_spinor<F64>(const_cast<void *>(dev_y), geo.V, n_rhs), dg, n_rhs,
                        (double2 *)dev_grad_U);
     WDT_HIP(hipGetLastError());
-    WDT_HIP(hipFreeAsync(dg, st));
     // df/dm0 = -y^dag x per RHS: the slice contraction of (y, x) summed over t
     const int Lt = geo.L[3];
     std::vector<double2> yx((size_t)n_rhs * Lt);

@@ -126,6 +126,24 @@ struct LaunchTuning {
 };
 LaunchTuning &tuning();
 
+// Stream-ordered scratch that is released on every path out of a scope.
+struct AsyncScratch {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    explicit AsyncScratch(hipStream_t st) : s(st) {}
+    ~AsyncScratch() {
+        if (p) (void)hipFreeAsync(p, s);
+    }
+    bool alloc(size_t bytes) {
+        if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            return false;
+        }
+        return true;
+    }
+};
+
 // Epilogues of the operator kernel.
 enum Epi { EPI_NONE = 0, EPI_DOT_AUX = 1, EPI_DOT_TS = 2, EPI_RESID = 3, EPI_DOT_TSR = 4 };
 
