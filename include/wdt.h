@@ -288,6 +288,8 @@ typedef struct {
  *                   {-1,-1,-1} off
  *  wave_per_site    1: the operator gives each site one wavefront (its 64
  *                   lanes are the RHS; batches of 48 or 64); 0 off; -1 automatic
+ *  even_odd         solvers: 1 or -1 (automatic) precondition even-odd on
+ *                   lattices with every extent even, 0 solve the full system
  * Invalid combinations for a lattice fall back to the automatic choice.
  * Process-wide; not thread-safe.
  */
@@ -295,6 +297,7 @@ typedef struct {
     int32_t rhs_tile, sites_per_block, max_blocks, z_slab, serial_tiles, t_chunk;
     int32_t brick[3];
     int32_t wave_per_site;
+    int32_t even_odd;
 } wdt_launch_shape;
 int wdt_set_launch_shape(const wdt_launch_shape *shape);
 

@@ -299,6 +299,9 @@ int wdt_set_launch_shape(const wdt_launch_shape *sh) {
     WDT_CHECK(sh->wave_per_site >= -1 && sh->wave_per_site <= 1,
               "wdt_set_launch_shape: wave_per_site must be -1, 0 or 1");
     t.wps = sh->wave_per_site;
+    WDT_CHECK(sh->even_odd >= -1 && sh->even_odd <= 1,
+              "wdt_set_launch_shape: even_odd must be -1, 0 or 1");
+    t.eo = sh->even_odd;
     return WDT_OK;
 }
 

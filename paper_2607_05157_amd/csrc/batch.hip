@@ -66,7 +66,8 @@ template <int EPI>
 __global__ __launch_bounds__(256) void kb_dslash(const SysDesc *sys, int nsys, int in, int out,
                                                  int aux) {
     WDT_SYS_CTX
-    dslash_body<F64, 0, false, EPI>(d.g, d.U, d.diag, sp(in), sp(out), sp(aux >= 0 ? aux : in),
+    dslash_body<F64, 0, false, EPI>(d.g, d.U, sp(in), d.diag, -0.5, sp(in), sp(out),
+                                    sp(aux >= 0 ? aux : in),
                                     d.N, d.NT, d.SB, d.part, tile, tile + 1, lb, d.G);
 }
 

@@ -49,6 +49,10 @@ struct Geom {
     // or, when bx > 0, bricks of bx*by*bz columns marched through all of t.
     int bz, bt;
     int bx, by;
+    // parity >= 0: kernels visit only the sites with (x+y+z+t) % 2 == parity
+    // (all extents even), nsites = V/2; parity < 0: all sites, nsites = V.
+    int parity;
+    int nsites;
 };
 
 // Site index of processing position p.  The lattice is cut into tiles of
@@ -57,6 +61,14 @@ struct Geom {
 // directions (a t-neighbour is Lx*Ly*bz positions away instead of Lx*Ly*Lz),
 // which lets an XCD's L2 serve the neighbour re-reads of the operator.
 __device__ __forceinline__ int site_of(const Geom &g, int p) {
+    if (g.parity >= 0) {
+        // the p-th site of the parity: sites 2p and 2p+1 lie in one x-row
+        // (Lx even) and have opposite parities; the row's (y, z, t) decide
+        const int s0 = 2 * p;
+        const int q = s0 / g.L[0];
+        const int rowpar = (q ^ (q / g.L[1]) ^ (q / (g.L[1] * g.L[2]))) & 1;
+        return s0 + (rowpar != g.parity ? 1 : 0);
+    }
     if (g.bx > 0) {
         // brick order: brick by brick, each brick one time slice after the
         // other, x fastest inside a slice of the brick
@@ -404,11 +416,11 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     const bool live = (ry < SB) && (r < N);                                \
     const int Lb = (LB);                                                   \
     const int Gb = (GB);                                                   \
-    const Sweep sw_ = sweep((g.V + SB - 1) / SB, Lb, Gb);                  \
+    const Sweep sw_ = sweep((g.nsites + SB - 1) / SB, Lb, Gb);             \
     if (live)                                                              \
         for (int grp = sw_.first; grp < sw_.end; grp += sw_.step) {        \
             const int p_ = grp * SB + ry;                                  \
-            if (p_ >= g.V) break;                                          \
+            if (p_ >= g.nsites) break;                                     \
             const int s = site_of(g, p_);
 
 #define SITE_LOOP_BEGIN SITE_LOOP_BEGIN_AT(blockIdx.y, xcd_block(blockIdx.x, gridDim.x), gridDim.x)

@@ -31,14 +31,15 @@ namespace wdt {
 
 template <class S, int NC, bool DAG, int EPI, bool WPS = false>
 __global__ __launch_bounds__(256) void k_dslash(Geom g, const typename S::link *__restrict__ U,
-                                                typename S::real diag, SpinorPtr<S> in,
+                                                SpinorPtr<S> self, typename S::real cs,
+                                                typename S::real ch, SpinorPtr<S> in,
                                                 SpinorPtr<S> out, SpinorPtr<S> aux, int N, int NT,
                                                 int SB, double2 *__restrict__ partials,
                                                 int serial_tiles) {
     const int t0 = serial_tiles > 0 ? 0 : (int)blockIdx.y;
     const int t1 = serial_tiles > 0 ? serial_tiles : t0 + 1;
-    dslash_body<S, NC, DAG, EPI, WPS>(g, U, diag, in, out, aux, N, NT, SB, partials, t0, t1,
-                                      xcd_block(blockIdx.x, gridDim.x), gridDim.x);
+    dslash_body<S, NC, DAG, EPI, WPS>(g, U, self, cs, ch, in, out, aux, N, NT, SB, partials, t0,
+                                      t1, xcd_block(blockIdx.x, gridDim.x), gridDim.x);
 }
 
 template <class S, int NC, bool DAG, int EPI, bool WPS = false>
@@ -58,69 +59,90 @@ template <class S> static int prec_of() {
     return std::is_same<S, F64>::value ? WDT_FP64 : std::is_same<S, F32>::value ? WDT_FP32 : WDT_FP16;
 }
 
+template <class S>
+struct HopPtrs {
+    SpinorPtr<S> self, in, out, aux;
+    typename S::real cs, ch;
+};
+
 template <class S, int NC, bool DAG, int EPI>
 static void launch_k(dim3 grid, int threads, hipStream_t stream, const Geom &g,
-                     const typename S::link *U, typename S::real diag, SpinorPtr<S> pin_,
-                     SpinorPtr<S> pout, SpinorPtr<S> paux, int N, int NT, int SB, double2 *part,
-                     int serial_tiles, int tc, int4 brick, bool wps) {
+                     const typename S::link *U, const HopPtrs<S> &h, int N, int NT, int SB,
+                     double2 *part, int serial_tiles, int tc, int4 brick, bool wps) {
+    // the t-march covers the whole lattice with the operator's own form
+    const bool march = tc > 0 && g.parity < 0 && h.self.p == h.in.p && h.ch == (typename S::real)(-0.5);
     if constexpr (NC == 48 || NC == 64) {
-        if (wps && tc == 0) {
+        if (wps && !march) {
             hipLaunchKernelGGL((k_dslash<S, NC, DAG, EPI, true>), grid, dim3(threads), 0, stream,
-                               g, U, diag, pin_, pout, paux, N, NT, SB, part, serial_tiles);
+                               g, U, h.self, h.cs, h.ch, h.in, h.out, h.aux, N, NT, SB, part,
+                               serial_tiles);
             return;
         }
-        if (wps && tc > 0) {
+        if (wps && march) {
             hipLaunchKernelGGL((k_dslash_march<S, NC, DAG, EPI, true>), grid, dim3(threads), 0,
-                               stream, g, U, diag, pin_, pout, paux, N, NT, SB, tc, brick, part);
+                               stream, g, U, h.cs, h.in, h.out, h.aux, N, NT, SB, tc, brick, part);
             return;
         }
     }
-    if (tc > 0)
+    if (march)
         hipLaunchKernelGGL((k_dslash_march<S, NC, DAG, EPI>), grid, dim3(threads), 0, stream, g,
-                           U, diag, pin_, pout, paux, N, NT, SB, tc, brick, part);
+                           U, h.cs, h.in, h.out, h.aux, N, NT, SB, tc, brick, part);
     else
         hipLaunchKernelGGL((k_dslash<S, NC, DAG, EPI>), grid, dim3(threads), 0, stream, g, U,
-                           diag, pin_, pout, paux, N, NT, SB, part, serial_tiles);
+                           h.self, h.cs, h.ch, h.in, h.out, h.aux, N, NT, SB, part, serial_tiles);
 }
 
 template <class S, bool DAG, int EPI>
-static int launch_t(const wdt_gauge_s *gf, double m0, const void *in, void *out, const void *aux,
-                    int N, double2 *partials, const Shape &sh, hipStream_t stream,
-                    const typename S::link *U) {
-    const Geom g = shaped_geom(gf->lat, sh);
+static int launch_t(const wdt_gauge_s *gf, const HopSpec &hs, const void *in, void *out,
+                    const void *aux, int N, double2 *partials, const Shape &sh0,
+                    hipStream_t stream, const typename S::link *U) {
+    Shape sh = sh0;
+    Geom g = shaped_geom(gf->lat, sh);
     const int V = g.V;
+    if (hs.parity >= 0) {
+        // one parity, plain order (no bricks, no t-march)
+        g = gf->lat.geom();
+        g.parity = hs.parity;
+        g.nsites = V / 2;
+        sh.tc = 0;
+    }
     // one site per wavefront: 64 lanes per site, four sites per block
     const bool wps = sh.wps && (nc_of(N) == 48 || nc_of(N) == 64);
     const int NT = wps ? 64 : sh.NT, SB = wps ? 4 : sh.SB, threads = wps ? 256 : sh.threads;
     const int tiles = (N + NT - 1) / NT;
     const dim3 grid(sh.G, (sh.serial && sh.tc == 0) ? 1 : tiles);
     const int serial_tiles = sh.serial ? tiles : 0;
-    SpinorPtr<S> pin_ = make_spinor<S>(const_cast<void *>(in), V, N);
-    SpinorPtr<S> pout = make_spinor<S>(out, V, N);
-    SpinorPtr<S> paux = make_spinor<S>(const_cast<void *>(aux), V, N);
+    HopPtrs<S> h;
+    h.in = make_spinor<S>(const_cast<void *>(in), V, N);
+    h.self = make_spinor<S>(const_cast<void *>(hs.self ? hs.self : in), V, N);
+    h.out = make_spinor<S>(out, V, N);
+    h.aux = make_spinor<S>(const_cast<void *>(aux), V, N);
+    h.cs = (typename S::real)hs.cs;
+    h.ch = (typename S::real)hs.ch;
     const int prec = prec_of<S>();
     static const char *names[3] = {"dslash_fp64", "dslash_fp32", "dslash_fp16"};
-    const int nvec = (EPI == EPI_DOT_AUX || EPI == EPI_RESID || EPI == EPI_DOT_TSR) ? 3 : 2;
+    // algorithmic bytes: in, out, a separate self, the epilogue's vector, links once
+    const int nvec = 2 + ((hs.cs != 0.0 && hs.self && hs.self != in) ? 1 : 0) +
+                     ((EPI == EPI_DOT_AUX || EPI == EPI_RESID || EPI == EPI_DOT_TSR) ? 1 : 0);
     ProfScope prof(names[prec],
-                   (double)V * ((double)N * nvec * site_bytes(prec) + 4.0 * link_bytes(prec)),
+                   (double)g.nsites * N * nvec * site_bytes(prec) + 4.0 * V * link_bytes(prec),
                    stream);
-    const typename S::real diag = (typename S::real)(4.0 + m0);
     switch (nc_of(N)) {
         case 16:
-            launch_k<S, 16, DAG, EPI>(grid, threads, stream, g, U, diag, pin_, pout, paux, N,
-                                     NT, SB, partials, serial_tiles, sh.tc, sh.brick, sh.wps);
+            launch_k<S, 16, DAG, EPI>(grid, threads, stream, g, U, h, N, NT, SB, partials,
+                                     serial_tiles, sh.tc, sh.brick, sh.wps);
             break;
         case 48:
-            launch_k<S, 48, DAG, EPI>(grid, threads, stream, g, U, diag, pin_, pout, paux, N,
-                                     NT, SB, partials, serial_tiles, sh.tc, sh.brick, sh.wps);
+            launch_k<S, 48, DAG, EPI>(grid, threads, stream, g, U, h, N, NT, SB, partials,
+                                     serial_tiles, sh.tc, sh.brick, sh.wps);
             break;
         case 64:
-            launch_k<S, 64, DAG, EPI>(grid, threads, stream, g, U, diag, pin_, pout, paux, N,
-                                     NT, SB, partials, serial_tiles, sh.tc, sh.brick, sh.wps);
+            launch_k<S, 64, DAG, EPI>(grid, threads, stream, g, U, h, N, NT, SB, partials,
+                                     serial_tiles, sh.tc, sh.brick, sh.wps);
             break;
         default:
-            launch_k<S, 0, DAG, EPI>(grid, threads, stream, g, U, diag, pin_, pout, paux, N,
-                                    NT, SB, partials, serial_tiles, sh.tc, sh.brick, sh.wps);
+            launch_k<S, 0, DAG, EPI>(grid, threads, stream, g, U, h, N, NT, SB, partials,
+                                    serial_tiles, sh.tc, sh.brick, sh.wps);
             break;
     }
     WDT_HIP(hipGetLastError());
@@ -128,38 +150,52 @@ static int launch_t(const wdt_gauge_s *gf, double m0, const void *in, void *out,
 }
 
 template <class S>
-static int launch_p(const wdt_gauge_s *gf, double m0, int dagger, int epi, const void *in,
-                    void *out, const void *aux, int N, double2 *partials, const Shape &sh,
-                    hipStream_t stream, const typename S::link *U) {
-#define WDT_EPI_CASE(E)                                                                      \
-    case E:                                                                                  \
-        return dagger ? launch_t<S, true, E>(gf, m0, in, out, aux, N, partials, sh, stream, U) \
-                      : launch_t<S, false, E>(gf, m0, in, out, aux, N, partials, sh, stream, U);
+static int launch_p(const wdt_gauge_s *gf, const HopSpec &hs, int dagger, int epi,
+                    const void *in, void *out, const void *aux, int N, double2 *partials,
+                    const Shape &sh, hipStream_t stream, const typename S::link *U) {
+#define WDT_EPI_CASE(E)                                                                          \
+    case E:                                                                                      \
+        return dagger ? launch_t<S, true, E>(gf, hs, in, out, aux, N, partials, sh, stream, U)   \
+                      : launch_t<S, false, E>(gf, hs, in, out, aux, N, partials, sh, stream, U);
     switch (epi) {
         WDT_EPI_CASE(EPI_NONE)
         WDT_EPI_CASE(EPI_DOT_AUX)
         WDT_EPI_CASE(EPI_DOT_TS)
         WDT_EPI_CASE(EPI_RESID)
         WDT_EPI_CASE(EPI_DOT_TSR)
+        WDT_EPI_CASE(EPI_NORM)
         default:
             return set_error(WDT_EINVAL, "bad operator epilogue %d", epi);
     }
 #undef WDT_EPI_CASE
 }
 
-int launch_dslash(const wdt_gauge_s *g, double m0, int prec, int dagger, int epi, const void *in,
-                  void *out, const void *aux, int N, double2 *partials, const Shape &sh,
-                  hipStream_t stream) {
+int launch_hop(const wdt_gauge_s *g, int prec, int dagger, int epi, const HopSpec &hs,
+               const void *in, void *out, const void *aux, int N, double2 *partials,
+               const Shape &sh, hipStream_t stream) {
+    if (hs.parity >= 0 && !g->lat.even_odd_ok())
+        return set_error(WDT_EINVAL, "one-parity operator on a lattice with an odd extent");
     switch (prec) {
         case WDT_FP64:
-            return launch_p<F64>(g, m0, dagger, epi, in, out, aux, N, partials, sh, stream, g->U64);
+            return launch_p<F64>(g, hs, dagger, epi, in, out, aux, N, partials, sh, stream, g->U64);
         case WDT_FP32:
-            return launch_p<F32>(g, m0, dagger, epi, in, out, aux, N, partials, sh, stream, g->U32);
+            return launch_p<F32>(g, hs, dagger, epi, in, out, aux, N, partials, sh, stream, g->U32);
         case WDT_FP16:
-            return launch_p<F16>(g, m0, dagger, epi, in, out, aux, N, partials, sh, stream, g->U16);
+            return launch_p<F16>(g, hs, dagger, epi, in, out, aux, N, partials, sh, stream, g->U16);
         default:
             return set_error(WDT_EINVAL, "bad precision %d", prec);
     }
+}
+
+int launch_dslash(const wdt_gauge_s *g, double m0, int prec, int dagger, int epi, const void *in,
+                  void *out, const void *aux, int N, double2 *partials, const Shape &sh,
+                  hipStream_t stream) {
+    HopSpec hs;
+    hs.parity = -1;
+    hs.self = in;
+    hs.cs = 4.0 + m0;
+    hs.ch = -0.5;
+    return launch_hop(g, prec, dagger, epi, hs, in, out, aux, N, partials, sh, stream);
 }
 
 // Resident blocks per CU of the operator kernel (the solve-time variant),

@@ -16,6 +16,10 @@ struct wdt_lattice_s {
     int bc_t;
     int64_t V;
     int device;
+    // every extent even: the checkerboard is consistent across the wrap
+    bool even_odd_ok() const {
+        return dims[0] % 2 == 0 && dims[1] % 2 == 0 && dims[2] % 2 == 0 && dims[3] % 2 == 0;
+    }
     wdt::Geom geom() const {
         wdt::Geom g;
         for (int i = 0; i < 4; ++i) g.L[i] = dims[i];
@@ -29,6 +33,8 @@ struct wdt_lattice_s {
         g.bz = dims[2];
         g.bt = dims[3];
         g.bx = g.by = 0;
+        g.parity = -1;
+        g.nsites = g.V;
         return g;
     }
 };
@@ -123,6 +129,7 @@ struct LaunchTuning {
     int tchunk = -1;  // operator marches along t in chunks of this many slices: 0 off, -1 automatic
     int brick = 0;    // sweep order bricks: 0 automatic, -1 off, else x*10000 + y*100 + z
     int wps = -1;     // operator one site per wavefront: 1 on, 0 off, -1 automatic
+    int eo = -1;      // solvers: even-odd preconditioning 1 on, 0 off, -1 automatic
 };
 LaunchTuning &tuning();
 
@@ -145,7 +152,8 @@ struct AsyncScratch {
 };
 
 // Epilogues of the operator kernel.
-enum Epi { EPI_NONE = 0, EPI_DOT_AUX = 1, EPI_DOT_TS = 2, EPI_RESID = 3, EPI_DOT_TSR = 4 };
+enum Epi { EPI_NONE = 0, EPI_DOT_AUX = 1, EPI_DOT_TS = 2, EPI_RESID = 3, EPI_DOT_TSR = 4,
+           EPI_NORM = 5 };
 
 // out = D in (or D^dag in); optional fused per-RHS dot partials written to
 // partials[(d*G + block)*N + r] as complex doubles.
@@ -153,8 +161,21 @@ enum Epi { EPI_NONE = 0, EPI_DOT_AUX = 1, EPI_DOT_TS = 2, EPI_RESID = 3, EPI_DOT
 //  EPI_DOT_TS:  d0 = out^dag in, d1 = ||out||^2
 //  EPI_DOT_TSR: as EPI_DOT_TS, and d2 = aux^dag out
 //  EPI_RESID:   out = aux - D in; d0 = ||out||^2, d1 = ||aux||^2
+//  EPI_NORM:    d0 = d1 = ||out||^2
 int launch_dslash(const wdt_gauge_s *g, double m0, int prec, int dagger, int epi,
                   const void *in, void *out, const void *aux, int N, double2 *partials,
                   const Shape &sh, hipStream_t stream);
+
+// The general form out = cs * self + ch * H in (H the hop sum of D: D = (4 + m0)
+// - H / 2) on the sites of one parity (parity 0 or 1; lattices with every
+// extent even) or on all sites (parity -1).  self = nullptr means in.
+struct HopSpec {
+    int parity = -1;
+    const void *self = nullptr;
+    double cs = 0.0, ch = 1.0;
+};
+int launch_hop(const wdt_gauge_s *g, int prec, int dagger, int epi, const HopSpec &hs,
+               const void *in, void *out, const void *aux, int N, double2 *partials,
+               const Shape &sh, hipStream_t stream);
 
 }  // namespace wdt

@@ -272,6 +272,18 @@ __device__ __forceinline__ void scalar_omega_beta_body(RhsState *st, const doubl
     }
 }
 
+// rho = the squared norm in partials slot 0 (the start of an iteration whose
+// shadow vector is the current residual).
+__device__ __forceinline__ void scalar_rho_body(RhsState *st, const double2 *partials, int G,
+                                                int N, int r) {
+    const double2 nn = block_sum(partials, 0, G, N, r);
+    if (threadIdx.x == 0) {
+        RhsState s = st[r];
+        s.rho = make_double2(nn.x, 0.0);
+        st[r] = s;
+    }
+}
+
 // After the fused update: ||r||^2, convergence and the iteration count.
 __device__ __forceinline__ void scalar_check_body(RhsState *st, const double2 *partials, int G,
                                                   int N, int r) {
@@ -612,21 +624,24 @@ __device__ __forceinline__ void epi_reduce(double2 (&red)[3][256], int tid, int 
     }
 }
 
-// Output of one site from the hop sum and the (scaled) own spinor, with the
-// epilogue's dot contributions; stores the result.
+// Output of one site, out = cs * c + ch * acc (c: the site's spinor of the
+// self vector, acc: the hop sum), with the epilogue's dot contributions;
+// stores the result.  The operator itself is cs = 4 + m0, ch = -1/2.
 //  EPI_DOT_AUX: d0 += aux^dag out
 //  EPI_DOT_TS:  d0 += out^dag in, d1 += ||out||^2
 //  EPI_DOT_TSR: as EPI_DOT_TS, and d2 += aux^dag out
 //  EPI_RESID:   out = aux - D in; d0 += ||out||^2, d1 += ||aux||^2
+//  EPI_NORM:    d0 += ||out||^2, d1 += ||out||^2
 template <class S, int NC, int EPI>
-__device__ __forceinline__ void finish_site(typename S::real diag, const cplx<typename S::real> (&c)[12],
+__device__ __forceinline__ void finish_site(typename S::real cs, typename S::real ch,
+                                            const cplx<typename S::real> (&c)[12],
                                             const cplx<typename S::real> (&acc)[12], SpinorPtr<S> out,
                                             SpinorPtr<S> aux, int s, int r, EpiAcc &e) {
     using R = typename S::real;
     cplx<R> o[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k)
-        o[k] = {diag * c[k].re - R(0.5) * acc[k].re, diag * c[k].im - R(0.5) * acc[k].im};
+        o[k] = {cs * c[k].re + ch * acc[k].re, cs * c[k].im + ch * acc[k].im};
     if constexpr (EPI == EPI_RESID) {
         cplx<R> b[12];
         WDT_AUX_LOAD<S, NC>(aux, s, r, b);
@@ -643,6 +658,13 @@ __device__ __forceinline__ void finish_site(typename S::real diag, const cplx<ty
         for (int k = 0; k < 12; ++k) {
             e.d0r += (double)a[k].re * o[k].re + (double)a[k].im * o[k].im;
             e.d0i += (double)a[k].re * o[k].im - (double)a[k].im * o[k].re;
+        }
+    } else if constexpr (EPI == EPI_NORM) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const double n = (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
+            e.d0r += n;
+            e.d1r += n;
         }
     } else if constexpr (EPI == EPI_DOT_TS || EPI == EPI_DOT_TSR) {
 #pragma unroll
@@ -668,9 +690,14 @@ __device__ __forceinline__ void finish_site(typename S::real diag, const cplx<ty
 // so the site, its neighbours and the link addresses are wave-uniform; the
 // links then come through the scalar cache into SGPRs instead of occupying
 // the vector memory pipeline with 64 copies of the same address.
+//
+// General form: out(s) = cs * self(s) + ch * H(in)(s), H the hop sum, over
+// the sites of g (one parity when g.parity >= 0); the operator D is
+// self = in, cs = 4 + m0, ch = -1/2.  cs = 0 skips the self load.
 template <class S, int NC, bool DAG, int EPI, bool WPS = false>
 __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::link *__restrict__ U,
-                                            typename S::real diag, SpinorPtr<S> in,
+                                            SpinorPtr<S> self, typename S::real cs,
+                                            typename S::real ch, SpinorPtr<S> in,
                                             SpinorPtr<S> out, SpinorPtr<S> aux, int N, int NT,
                                             int SB, double2 *__restrict__ partials, int tile0,
                                             int tile1, int Lb, int Gb) {
@@ -680,7 +707,7 @@ __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::lin
     const int tid = threadIdx.x;
     const int rl = WPS ? (tid & 63) : tid % NT;
     const int ry = WPS ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid / NT;
-    const Sweep sw = sweep((g.V + SB - 1) / SB, Lb, Gb);
+    const Sweep sw = sweep((g.nsites + SB - 1) / SB, Lb, Gb);
     // RHS tiles [tile0, tile1) one after the other: the XCD's L2 then holds
     // one tile's worth of each site instead of the whole batch
     for (int tile = tile0; tile < tile1; ++tile) {
@@ -690,7 +717,7 @@ __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::lin
     if (live) {
         for (int grp = sw.first; grp < sw.end; grp += sw.step) {
             const int p = grp * SB + ry;
-            if (p >= g.V) break;
+            if (p >= g.nsites) break;
             const int s = site_of(g, p);
             const SiteNbr nb = neighbours(g, s);
             cplx<R> acc[12];
@@ -701,8 +728,13 @@ __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::lin
             hop_pair<2, DAG, PIN, NC, S>(g, U, in, s, nb, r, acc);
             hop_pair<3, DAG, PIN, NC, S>(g, U, in, s, nb, r, acc);
             cplx<R> c[12];
-            load_site<S, NC>(in, s, r, c);
-            finish_site<S, NC, EPI>(diag, c, acc, out, aux, s, r, e);
+            if (cs != R(0)) {
+                load_site<S, NC>(self, s, r, c);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) c[k] = {R(0), R(0)};
+            }
+            finish_site<S, NC, EPI>(cs, ch, c, acc, out, aux, s, r, e);
         }
     }
     if constexpr (EPI != EPI_NONE) {
@@ -822,7 +854,7 @@ __device__ __forceinline__ void dslash_march_body(const Geom &g, const typename 
 #pragma unroll
                     for (int k = 0; k < 12; ++k) cc[k] = {cc[k].re * sc, cc[k].im * sc};
                 }
-                finish_site<S, NC, EPI>(diag, cc, acc, out, aux, s, r, e);
+                finish_site<S, NC, EPI>(diag, R(-0.5), cc, acc, out, aux, s, r, e);
 #pragma unroll
                 for (int k = 0; k < 12; ++k) ec[k] = en[k];
                 sc = sn;

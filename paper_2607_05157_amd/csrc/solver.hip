@@ -39,6 +39,9 @@ __global__ void k_scalar_omega_beta(RhsState *st, const double2 *partials, int G
 __global__ void k_scalar_check(RhsState *st, const double2 *partials, int G, int N) {
     scalar_check_body(st, partials, G, N, blockIdx.x);
 }
+__global__ void k_scalar_rho(RhsState *st, const double2 *partials, int G, int N) {
+    scalar_rho_body(st, partials, G, N, blockIdx.x);
+}
 
 #define WDT_BLOCK_CTX blockIdx.y, xcd_block(blockIdx.x, gridDim.x), gridDim.x
 
@@ -312,7 +315,71 @@ struct Bicg {
     hipStream_t stream;
     RhsState *st;
     double2 *part;
+    bool eo = false;  // iterate on the even-site Schur complement
 };
+
+// Even-odd preconditioning: on when every extent is even, unless the tuner
+// switches it off.
+bool use_even_odd(const wdt_lattice_s &lat) {
+    const int eo = tuning().eo;
+    return lat.even_odd_ok() && eo != 0;
+}
+
+// The geometry of the sites of one parity, in plain order.
+Geom parity_geom(const wdt_lattice_s &lat, int parity) {
+    Geom g = lat.geom();
+    g.parity = parity;
+    g.nsites = (int)(lat.V / 2);
+    return g;
+}
+
+// Even-odd (Schur) preconditioning on a lattice with every extent even.
+// With a = 4 + m0 and H the hop sum (D = a - H/2), the odd sites are
+// eliminated:
+//   M x_e = a x_e - (1/(4a)) H_eo H_oe x_e = b_e + (1/(2a)) H_eo b_o =: b'_e,
+//   x_o = (1/a) b_o + (1/(2a)) H_oe x_e.
+// The residual of x = (x_e, x_o) is then b'_e - M x_e on the even sites and
+// exactly zero on the odd ones, so the Schur residual is the true residual.
+// Vectors keep the full-lattice layout; the iteration touches even sites only
+// and uses the odd sites of its output vector as scratch for H_oe x_e.
+int apply_op(Bicg &B, int prec, int epi, const void *in, void *out, const void *aux) {
+    if (!B.eo)
+        return launch_dslash(B.g, B.m0, prec, 0, epi, in, out, aux, B.N, B.part, B.sh, B.stream);
+    const double a = 4.0 + B.m0;
+    HopSpec h1;
+    h1.parity = 1;
+    h1.cs = 0.0;
+    h1.ch = 1.0;
+    WDT_TRY(launch_hop(B.g, prec, 0, EPI_NONE, h1, in, out, nullptr, B.N, nullptr, B.sh, B.stream));
+    HopSpec h2;
+    h2.parity = 0;
+    h2.self = in;
+    h2.cs = a;
+    h2.ch = -1.0 / (4.0 * a);
+    return launch_hop(B.g, prec, 0, epi, h2, out, out, aux, B.N, B.part, B.sh, B.stream);
+}
+
+// r_e += (1/(2a)) H_eo r_o in place: the Schur right-hand side of the
+// correction equation; partials d0 = d1 = ||r_e||^2.
+int schur_rhs(Bicg &B, int prec, void *r) {
+    HopSpec h;
+    h.parity = 0;
+    h.self = r;
+    h.cs = 1.0;
+    h.ch = 1.0 / (2.0 * (4.0 + B.m0));
+    return launch_hop(B.g, prec, 0, EPI_NORM, h, r, r, nullptr, B.N, B.part, B.sh, B.stream);
+}
+
+// x_o = (1/a) b_o + (1/(2a)) H_oe x_e in place on the odd sites of x.
+int schur_odd(Bicg &B, int prec, const void *b, void *x) {
+    const double a = 4.0 + B.m0;
+    HopSpec h;
+    h.parity = 1;
+    h.self = b;
+    h.cs = 1.0 / a;
+    h.ch = 1.0 / (2.0 * a);
+    return launch_hop(B.g, prec, 0, EPI_NONE, h, x, x, nullptr, B.N, nullptr, B.sh, B.stream);
+}
 
 // Runs BiCGStab iterations in storage S until every RHS is inactive or
 // `max_iter` is reached.  x, r, rhat, p, v, s, t are S-format vectors; the
@@ -326,7 +393,7 @@ int bicgstab_iterate(Bicg &B, int prec, void *x, void *r, void *rhat, void *p, v
     int it = 0;
     // p = r
     WDT_HIP(hipMemcpyAsync(p, r, spinor_bytes(V, N, prec), hipMemcpyDeviceToDevice, B.stream));
-    const double vb = (double)V * N * site_bytes(prec);  // one vector pass
+    const double vb = (double)B.geo.nsites * N * site_bytes(prec);  // one vector pass
     static const char *nm_s[3] = {"axpy_s_fp64", "axpy_s_fp32", "axpy_s_fp16"};
     static const char *nm_xr[3] = {"update_xr_fp64", "update_xr_fp32", "update_xr_fp16"};
     static const char *nm_p[3] = {"update_p_fp64", "update_p_fp32", "update_p_fp16"};
@@ -334,7 +401,7 @@ int bicgstab_iterate(Bicg &B, int prec, void *x, void *r, void *rhat, void *p, v
     // the inner solves of the mixed solver take the fused end of iteration
     constexpr bool fused = !std::is_same<S, F64>::value;
     while (it < max_iter) {
-        WDT_TRY(launch_dslash(B.g, B.m0, prec, 0, EPI_DOT_AUX, p, v, rhat, N, B.part, sh, B.stream));
+        WDT_TRY(apply_op(B, prec, EPI_DOT_AUX, p, v, rhat));
         hipLaunchKernelGGL(k_scalar_alpha, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.G, N);
         {
             ProfScope pr(nm_s[prec], 3 * vb, B.stream);
@@ -343,8 +410,7 @@ int bicgstab_iterate(Bicg &B, int prec, void *x, void *r, void *rhat, void *p, v
                                sp<S>(s, V, N));
         }
         if constexpr (fused) {
-            WDT_TRY(launch_dslash(B.g, B.m0, prec, 0, EPI_DOT_TSR, s, t, rhat, N, B.part, sh,
-                                  B.stream));
+            WDT_TRY(apply_op(B, prec, EPI_DOT_TSR, s, t, rhat));
             hipLaunchKernelGGL(k_scalar_omega_beta, dim3(N), dim3(256), 0, B.stream, B.st, B.part,
                                sh.G, N);
             {
@@ -368,7 +434,7 @@ int bicgstab_iterate(Bicg &B, int prec, void *x, void *r, void *rhat, void *p, v
             }
             continue;
         }
-        WDT_TRY(launch_dslash(B.g, B.m0, prec, 0, EPI_DOT_TS, s, t, nullptr, N, B.part, sh, B.stream));
+        WDT_TRY(apply_op(B, prec, EPI_DOT_TS, s, t, nullptr));
         hipLaunchKernelGGL(k_scalar_omega, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.G, N);
         {
             ProfScope pr(nm_xr[prec], 7 * vb, B.stream);
@@ -419,6 +485,8 @@ static int solve_fp64(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
          *t = base + 5 * vb;
     Bicg B{g, m0, N, V, sh, geo, NT, dim3(sh.Gv, sh.tiles), stream,
            (RhsState *)(base + st_off), (double2 *)(base + part_off)};
+    B.eo = use_even_odd(g->lat);
+    if (B.eo) B.geo = parity_geom(g->lat, 0);
     WDT_HIP(hipMemsetAsync(B.st, 0, sizeof(RhsState) * N, stream));
     if (!P.x0_is_guess) WDT_HIP(hipMemsetAsync(x, 0, vb, stream));
     std::vector<RhsState> hs(N);
@@ -431,6 +499,11 @@ static int solve_fp64(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
         WDT_TRY(launch_dslash(g, m0, WDT_FP64, 0, EPI_RESID, x, r, b, N, B.part, sh, stream));
         hipLaunchKernelGGL(k_init_state, dim3(N), dim3(256), 0, stream, B.st, B.part, sh.G, N,
                            P.tol, (const int *)nullptr);
+        if (B.eo) {
+            // the correction solves M e_e = r_e + H_eo r_o / (2a); rho = its norm
+            WDT_TRY(schur_rhs(B, WDT_FP64, r));
+            hipLaunchKernelGGL(k_scalar_rho, dim3(N), dim3(256), 0, stream, B.st, B.part, sh.G, N);
+        }
         WDT_HIP(hipMemcpyAsync(rhat, r, vb, hipMemcpyDeviceToDevice, stream));
         WDT_HIP(hipMemcpyAsync(hs.data(), B.st, sizeof(RhsState) * N, hipMemcpyDeviceToHost, stream));
         WDT_HIP(hipStreamSynchronize(stream));
@@ -456,6 +529,7 @@ static int solve_fp64(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
         for (int k = 0; k < N; ++k) before[k] = hs[k].iters;
         int done = 0;
         WDT_TRY(bicgstab_iterate<F64>(B, WDT_FP64, x, r, rhat, p, v, s, t, budget, check, hs, &done));
+        if (B.eo) WDT_TRY(schur_odd(B, WDT_FP64, b, x));
         WDT_HIP(hipMemcpyAsync(hs.data(), B.st, sizeof(RhsState) * N, hipMemcpyDeviceToHost, stream));
         WDT_HIP(hipStreamSynchronize(stream));
         for (int k = 0; k < N; ++k) total_it[k] += hs[k].iters - before[k];
@@ -493,6 +567,8 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
     std::vector<double> hfac(2 * (size_t)((N + 31) / 32) * 32, 0.0);
     Bicg B{g, m0, N, V, sh, geo, NT, dim3(sh.Gv, sh.tiles), stream,
            (RhsState *)(base + st_off), (double2 *)(base + part_off)};
+    B.eo = use_even_odd(g->lat);
+    if (B.eo) B.geo = parity_geom(g->lat, 0);
     const dim3 grid(sh.Gv, sh.tiles);
     if (!P.x0_is_guess) WDT_HIP(hipMemsetAsync(x, 0, vb64, stream));
     std::vector<RhsState> hs(N);
@@ -547,17 +623,29 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
         hipLaunchKernelGGL((k_convert<F64, S, false>), grid, dim3(sh.threads), 0, stream, geo, N, NT,
                            sh.SB, sp<F64>(r64, V, N), sp<S>(rS, V, N), (const double *)fin);
         WDT_HIP(hipMemsetAsync(e, 0, vbl, stream));
-        // ||r||^2 in the stored precision: residual of e = 0 against rS
-        WDT_TRY(launch_dslash(g, m0, prec, 0, EPI_RESID, e, rhat, rS, N, B.part, sh, stream));
-        hipLaunchKernelGGL(k_init_state, dim3(N), dim3(256), 0, stream, B.st, B.part, sh.G, N,
-                           inner_tol, (const int *)mask);
-        WDT_HIP(hipMemcpyAsync(rS, rhat, spinor_bytes(V, N, prec), hipMemcpyDeviceToDevice, stream));
+        if (B.eo) {
+            // even-odd: the inner system is M e_e = rS_e + H_eo rS_o / (2a); the
+            // odd sites of rS keep rS_o for the reconstruction of e_o
+            WDT_TRY(schur_rhs(B, prec, rS));
+            hipLaunchKernelGGL(k_init_state, dim3(N), dim3(256), 0, stream, B.st, B.part, sh.G, N,
+                               inner_tol, (const int *)mask);
+            WDT_HIP(hipMemcpyAsync(rhat, rS, spinor_bytes(V, N, prec), hipMemcpyDeviceToDevice,
+                                   stream));
+        } else {
+            // ||r||^2 in the stored precision: residual of e = 0 against rS
+            WDT_TRY(launch_dslash(g, m0, prec, 0, EPI_RESID, e, rhat, rS, N, B.part, sh, stream));
+            hipLaunchKernelGGL(k_init_state, dim3(N), dim3(256), 0, stream, B.st, B.part, sh.G, N,
+                               inner_tol, (const int *)mask);
+            WDT_HIP(hipMemcpyAsync(rS, rhat, spinor_bytes(V, N, prec), hipMemcpyDeviceToDevice,
+                                   stream));
+        }
         std::vector<int> before(N);
         WDT_HIP(hipMemcpyAsync(hs.data(), B.st, sizeof(RhsState) * N, hipMemcpyDeviceToHost, stream));
         WDT_HIP(hipStreamSynchronize(stream));
         for (int k = 0; k < N; ++k) before[k] = hs[k].iters;
         int done = 0;
         WDT_TRY(bicgstab_iterate<S>(B, prec, e, rS, rhat, p, v, s, t, budget, check, hs, &done));
+        if (B.eo) WDT_TRY(schur_odd(B, prec, rS, e));
         WDT_HIP(hipMemcpyAsync(hs.data(), B.st, sizeof(RhsState) * N, hipMemcpyDeviceToHost, stream));
         WDT_HIP(hipStreamSynchronize(stream));
         for (int k = 0; k < N; ++k) total_it[k] += hs[k].iters - before[k];

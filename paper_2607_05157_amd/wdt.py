@@ -324,18 +324,19 @@ class LaunchShape(ctypes.Structure):
     _fields_ = [("rhs_tile", ctypes.c_int32), ("sites_per_block", ctypes.c_int32),
                 ("max_blocks", ctypes.c_int32), ("z_slab", ctypes.c_int32),
                 ("serial_tiles", ctypes.c_int32), ("t_chunk", ctypes.c_int32),
-                ("brick", ctypes.c_int32 * 3), ("wave_per_site", ctypes.c_int32)]
+                ("brick", ctypes.c_int32 * 3), ("wave_per_site", ctypes.c_int32),
+                ("even_odd", ctypes.c_int32)]
 
 
 def set_launch_shape(rhs_tile=0, sites_per_block=0, max_blocks=0, z_slab=0, serial_tiles=-1,
-                     t_chunk=-1, brick=(0, 0, 0), wave_per_site=-1):
+                     t_chunk=-1, brick=(0, 0, 0), wave_per_site=-1, even_odd=-1):
     """Override the launch shape of the (site, rhs) kernels (see wdt_launch_shape;
     the defaults restore the automatic choice)."""
     L = lib()
     L.wdt_set_launch_shape.restype = ctypes.c_int
     L.wdt_set_launch_shape.argtypes = [ctypes.POINTER(LaunchShape)]
     s = LaunchShape(rhs_tile, sites_per_block, max_blocks, z_slab, serial_tiles, t_chunk,
-                    (ctypes.c_int32 * 3)(*brick), wave_per_site)
+                    (ctypes.c_int32 * 3)(*brick), wave_per_site, even_odd)
     check(L.wdt_set_launch_shape(ctypes.byref(s)), "wdt_set_launch_shape")
 
 
