@@ -12,6 +12,12 @@
 // budget is dealt again over the systems that still have active RHS (finished
 // ones get none), which only rewrites the device-side system table between
 // graph replays.
+//
+// Systems whose lattice has every extent even are solved even-odd
+// preconditioned, like the single-system solver: the iteration runs on the
+// even sites with M = a - H_eo H_oe / (4a) (a = 4 + m0), the restart turns the
+// true residual into the Schur right-hand side, and the odd sites of x are
+// rebuilt from b and the even sites at the end of every round.
 #include "kernels.h"
 
 #include <algorithm>
@@ -27,6 +33,7 @@ struct SysDesc {
     Geom g;
     const double2 *U;
     double diag;
+    int eo;  // 1: even-odd preconditioned (every extent even)
     int N, NT, SB, tiles, G;
     int block_begin, nblocks;
     int rhs_begin;
@@ -62,6 +69,20 @@ __device__ __forceinline__ int find_rhs(const SysDesc *sys, int nsys, int rhs) {
     const int tile = lbg / d.G, lb = xcd_block(lbg - tile * d.G, d.G);     \
     auto sp = [&](int id) { return make_spinor<F64>(d.vec[id], d.g.V, d.N); };
 
+// The sites of one parity (parity >= 0) or all sites.
+__device__ __forceinline__ Geom sys_geom(const SysDesc &d, int parity) {
+    Geom g = d.g;
+    if (parity >= 0) {
+        g.parity = parity;
+        g.nsites = g.V / 2;
+    }
+    return g;
+}
+
+// The sites the iteration's vector updates touch: the even ones under even-odd.
+__device__ __forceinline__ Geom iter_geom(const SysDesc &d) { return sys_geom(d, d.eo ? 0 : -1); }
+
+// Full operator: out = D in (with the epilogue EPI), every system.
 template <int EPI>
 __global__ __launch_bounds__(256) void kb_dslash(const SysDesc *sys, int nsys, int in, int out,
                                                  int aux) {
@@ -71,25 +92,70 @@ __global__ __launch_bounds__(256) void kb_dslash(const SysDesc *sys, int nsys, i
                                     d.N, d.NT, d.SB, d.part, tile, tile + 1, lb, d.G);
 }
 
+// The iteration's operator, first half: even-odd systems put H_oe in on the
+// odd sites of out; the others do nothing here.
+__global__ __launch_bounds__(256) void kb_op_odd(const SysDesc *sys, int nsys, int in, int out) {
+    WDT_SYS_CTX
+    if (!d.eo) return;
+    dslash_body<F64, 0, false, EPI_NONE>(sys_geom(d, 1), d.U, sp(in), 0.0, 1.0, sp(in), sp(out),
+                                         sp(in), d.N, d.NT, d.SB, nullptr, tile, tile + 1, lb,
+                                         d.G);
+}
+
+// Second half: even-odd systems out_e = a in_e - H_eo out_o / (4a) (the Schur
+// operator); the others out = D in.
+template <int EPI>
+__global__ __launch_bounds__(256) void kb_op_even(const SysDesc *sys, int nsys, int in, int out,
+                                                  int aux) {
+    WDT_SYS_CTX
+    const SpinorPtr<F64> pa = sp(aux >= 0 ? aux : in);
+    if (d.eo)
+        dslash_body<F64, 0, false, EPI>(sys_geom(d, 0), d.U, sp(in), d.diag,
+                                        -0.25 / d.diag, sp(out), sp(out), pa, d.N, d.NT, d.SB,
+                                        d.part, tile, tile + 1, lb, d.G);
+    else
+        dslash_body<F64, 0, false, EPI>(d.g, d.U, sp(in), d.diag, -0.5, sp(in), sp(out), pa, d.N,
+                                        d.NT, d.SB, d.part, tile, tile + 1, lb, d.G);
+}
+
+// Even-odd systems: r_e += H_eo r_o / (2a) in place (the Schur right-hand
+// side of the correction equation), partials d0 = d1 = ||r_e||^2.
+__global__ __launch_bounds__(256) void kb_schur_rhs(const SysDesc *sys, int nsys) {
+    WDT_SYS_CTX
+    if (!d.eo) return;
+    dslash_body<F64, 0, false, EPI_NORM>(sys_geom(d, 0), d.U, sp(V_R), 1.0, 0.5 / d.diag,
+                                         sp(V_R), sp(V_R), sp(V_R), d.N, d.NT, d.SB, d.part,
+                                         tile, tile + 1, lb, d.G);
+}
+
+// Even-odd systems: x_o = b_o / a + H_oe x_e / (2a) in place.
+__global__ __launch_bounds__(256) void kb_schur_odd(const SysDesc *sys, int nsys) {
+    WDT_SYS_CTX
+    if (!d.eo) return;
+    dslash_body<F64, 0, false, EPI_NONE>(sys_geom(d, 1), d.U, sp(V_B), 1.0 / d.diag,
+                                         0.5 / d.diag, sp(V_X), sp(V_X), sp(V_X), d.N, d.NT,
+                                         d.SB, nullptr, tile, tile + 1, lb, d.G);
+}
+
 __global__ __launch_bounds__(256) void kb_update_s(const SysDesc *sys, int nsys,
                                                    const RhsState *st) {
     WDT_SYS_CTX
-    update_s_body<F64>(d.g, d.N, d.NT, d.SB, st + d.rhs_begin, sp(V_R), sp(V_V), sp(V_S), tile,
-                       lb, d.G);
+    update_s_body<F64>(iter_geom(d), d.N, d.NT, d.SB, st + d.rhs_begin, sp(V_R), sp(V_V), sp(V_S),
+                       tile, lb, d.G);
 }
 
 __global__ __launch_bounds__(256) void kb_update_xr(const SysDesc *sys, int nsys,
                                                     const RhsState *st) {
     WDT_SYS_CTX
-    update_xr_body<F64>(d.g, d.N, d.NT, d.SB, st + d.rhs_begin, sp(V_X), sp(V_P), sp(V_S),
-                        sp(V_T), sp(V_R), sp(V_RHAT), d.part, tile, lb, d.G);
+    update_xr_body<F64>(iter_geom(d), d.N, d.NT, d.SB, st + d.rhs_begin, sp(V_X), sp(V_P),
+                        sp(V_S), sp(V_T), sp(V_R), sp(V_RHAT), d.part, tile, lb, d.G);
 }
 
 __global__ __launch_bounds__(256) void kb_update_p(const SysDesc *sys, int nsys,
                                                    const RhsState *st) {
     WDT_SYS_CTX
-    update_p_body<F64>(d.g, d.N, d.NT, d.SB, st + d.rhs_begin, sp(V_R), sp(V_P), sp(V_V), tile,
-                       lb, d.G);
+    update_p_body<F64>(iter_geom(d), d.N, d.NT, d.SB, st + d.rhs_begin, sp(V_R), sp(V_P), sp(V_V),
+                       tile, lb, d.G);
 }
 
 // dst = src (or dst = 0 when src < 0)
@@ -131,6 +197,11 @@ __global__ void kb_omega(const SysDesc *sys, int nsys, RhsState *st) {
 __global__ void kb_beta(const SysDesc *sys, int nsys, RhsState *st) {
     WDT_RHS_CTX
     scalar_beta_body(s0, d.part, d.G, d.N, r);
+}
+// even-odd systems: rho = ||r_e||^2 of the Schur right-hand side
+__global__ void kb_rho(const SysDesc *sys, int nsys, RhsState *st) {
+    WDT_RHS_CTX
+    if (d.eo) scalar_rho_body(s0, d.part, d.G, d.N, r);
 }
 
 }  // namespace wdt
@@ -308,15 +379,17 @@ int upload(wdt_batch_s *b) {
     return WDT_OK;
 }
 
-// One BiCGStab iteration for every system (eight launches over grid_blocks
+// One BiCGStab iteration for every system (ten launches over grid_blocks
 // blocks; blocks past the last system's range return at once).
 int enqueue_iteration(wdt_batch_s *b) {
     const dim3 gb(b->grid_blocks), gr(b->total_rhs), t(256);
-    hipLaunchKernelGGL(kb_dslash<EPI_DOT_AUX>, gb, t, 0, b->stream, b->dev, b->nsys, (int)V_P,
+    hipLaunchKernelGGL(kb_op_odd, gb, t, 0, b->stream, b->dev, b->nsys, (int)V_P, (int)V_V);
+    hipLaunchKernelGGL(kb_op_even<EPI_DOT_AUX>, gb, t, 0, b->stream, b->dev, b->nsys, (int)V_P,
                        (int)V_V, (int)V_RHAT);
     hipLaunchKernelGGL(kb_alpha, gr, t, 0, b->stream, b->dev, b->nsys, b->st);
     hipLaunchKernelGGL(kb_update_s, gb, t, 0, b->stream, b->dev, b->nsys, b->st);
-    hipLaunchKernelGGL(kb_dslash<EPI_DOT_TS>, gb, t, 0, b->stream, b->dev, b->nsys, (int)V_S,
+    hipLaunchKernelGGL(kb_op_odd, gb, t, 0, b->stream, b->dev, b->nsys, (int)V_S, (int)V_T);
+    hipLaunchKernelGGL(kb_op_even<EPI_DOT_TS>, gb, t, 0, b->stream, b->dev, b->nsys, (int)V_S,
                        (int)V_T, -1);
     hipLaunchKernelGGL(kb_omega, gr, t, 0, b->stream, b->dev, b->nsys, b->st);
     hipLaunchKernelGGL(kb_update_xr, gb, t, 0, b->stream, b->dev, b->nsys, b->st);
@@ -349,12 +422,16 @@ int capture(wdt_batch_s *b) {
     return WDT_OK;
 }
 
-// r = b - D x, rhat = r, p = r, states from the true residual.
+// r = b - D x, states from the true residual; even-odd systems then take the
+// Schur right-hand side r_e + H_eo r_o / (2a) for r and its norm for rho;
+// rhat = r, p = r.
 int restart(wdt_batch_s *b, double tol) {
     const dim3 gb(b->total_blocks), gr(b->total_rhs), t(256);
     hipLaunchKernelGGL(kb_dslash<EPI_RESID>, gb, t, 0, b->stream, b->dev, b->nsys, (int)V_X,
                        (int)V_R, (int)V_B);
     hipLaunchKernelGGL(kb_init, gr, t, 0, b->stream, b->dev, b->nsys, b->st, tol);
+    hipLaunchKernelGGL(kb_schur_rhs, gb, t, 0, b->stream, b->dev, b->nsys);
+    hipLaunchKernelGGL(kb_rho, gr, t, 0, b->stream, b->dev, b->nsys, b->st);
     hipLaunchKernelGGL(kb_copy, gb, t, 0, b->stream, b->dev, b->nsys, (int)V_R, (int)V_RHAT);
     hipLaunchKernelGGL(kb_copy, gb, t, 0, b->stream, b->dev, b->nsys, (int)V_R, (int)V_P);
     WDT_HIP(hipGetLastError());
@@ -459,6 +536,7 @@ int wdt_batch_solve(wdt_batch b, void *const *dev_b, void *const *dev_x,
         WDT_CHECK(dev_b[i] && dev_x[i] && dev_b[i] != dev_x[i], "wdt_batch_solve: system %d", i);
         b->host[i].vec[V_B] = (double2 *)dev_b[i];
         b->host[i].vec[V_X] = (double2 *)dev_x[i];
+        b->host[i].eo = (b->gauges[i]->lat.even_odd_ok() && tuning().eo != 0) ? 1 : 0;
     }
     // the batch stream runs after the caller's stream, and the caller's after it
     StreamJoin join((hipStream_t)stream, b->stream);
@@ -540,6 +618,16 @@ int wdt_batch_solve(wdt_batch b, void *const *dev_b, void *const *dev_x,
                 WDT_TRY(redeal());
             }
         }
+        // odd sites of x from b and the even sites (a full-lattice launch:
+        // every system, dealt like the restart)
+        if (dealt != all) {
+            assign_blocks(b, all);
+            dealt = all;
+            WDT_TRY(upload(b));
+        }
+        hipLaunchKernelGGL(kb_schur_odd, dim3(b->total_blocks), dim3(256), 0, b->stream, b->dev,
+                           b->nsys);
+        WDT_HIP(hipGetLastError());
         WDT_HIP(hipMemcpyAsync(hs.data(), b->st, sizeof(RhsState) * b->total_rhs,
                                hipMemcpyDeviceToHost, b->stream));
         WDT_HIP(hipStreamSynchronize(b->stream));
