@@ -155,9 +155,13 @@ int wdt_apply_D(wdt_gauge g, double m0, const void *dev_in, void *dev_out,
  *   WDT_FP16 / WDT_FP32 - FP64 defect correction: r = b - D x in FP64, an
  *     inner BiCGStab on D e = r in FP32 arithmetic with vectors stored in
  *     FP16 (+ per-site-per-RHS scale) or FP32, then x += e in FP64.
+ * On a lattice with every extent even both iterate on the even-odd (Schur)
+ * system a x_e - H_eo H_oe x_e / (4a), a = 4 + m0, H the hop sum of D, and
+ * rebuild the odd sites from b and x_e (see wdt_launch_shape.even_odd).
  * Every RHS stops when its true FP64 relative residual ||b - D x|| / ||b||
  * is <= tol.  dev_b, dev_x: FP64 batches; x starts from 0 unless
- * x0_is_guess.  stats (host, may be NULL): n_rhs records.
+ * x0_is_guess.  stats (host, may be NULL): n_rhs records.  Uses two ints of
+ * host-mapped memory per gauge handle (allocated on first use).
  * Returns WDT_WNOTCONVERGED if some RHS did not reach tol in max_iter, or if
  * its true residual is not finite (an input holding inf or NaN).
  */
@@ -168,7 +172,11 @@ typedef struct {
     double inner_tol;    /* relative residual reduction per inner solve */
     int32_t max_outer;   /* cap on defect-correction steps */
     int32_t x0_is_guess; /* 1: dev_x holds a starting guess */
-    int32_t check_every; /* iterations between convergence checks on host */
+    int32_t check_every; /* wdt_batch_solve: iterations between convergence
+                            checks on the host.  wdt_solve checks after every
+                            iteration, one iteration behind the device (the
+                            iteration queued past convergence does no work),
+                            and ignores it */
 } wdt_solve_params;
 
 typedef struct {

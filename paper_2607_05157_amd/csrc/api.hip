@@ -52,6 +52,7 @@ struct ProfPending {
 };
 struct ProfState {
     bool on = false;
+    size_t drained = 0;  // entries drained so far (marks count from the start)
     std::vector<ProfClass> classes;
     std::vector<ProfPending> pending;
     std::vector<hipEvent_t> pool;
@@ -83,6 +84,7 @@ struct ProfState {
             if (p.a) pool.push_back(p.a);
             if (p.b) pool.push_back(p.b);
         }
+        drained += pending.size();
         pending.clear();
     }
 };
@@ -101,6 +103,18 @@ ProfScope::ProfScope(const char *name, double bytes, hipStream_t s) : stop(nullp
 
 ProfScope::~ProfScope() {
     if (stop) (void)hipEventRecord(stop, stream);
+}
+
+size_t prof_mark() { return g_prof.drained + g_prof.pending.size(); }
+
+void prof_discard(size_t mark) {
+    if (mark < g_prof.drained) return;  // already counted
+    const size_t keep = mark - g_prof.drained;
+    for (size_t i = keep; i < g_prof.pending.size(); ++i) {
+        if (g_prof.pending[i].a) g_prof.pool.push_back(g_prof.pending[i].a);
+        if (g_prof.pending[i].b) g_prof.pool.push_back(g_prof.pending[i].b);
+    }
+    if (keep < g_prof.pending.size()) g_prof.pending.resize(keep);
 }
 
 // Converts FP64 links to the FP32 copy (FP32 operator) and to the paired
@@ -262,6 +276,7 @@ int wdt_gauge_destroy(wdt_gauge g) {
     (void)hipFree(g->U32);
     (void)hipFree(g->U16);
     if (g->ws.ptr) (void)hipFree(g->ws.ptr);
+    if (g->live_host) (void)hipHostFree(g->live_host);
     delete g;
     return WDT_OK;
 }

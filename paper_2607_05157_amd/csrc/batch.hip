@@ -231,14 +231,6 @@ struct wdt_batch_s {
 
 namespace {
 
-// Destroys an event on every path out of a scope.
-struct EventGuard {
-    hipEvent_t e = nullptr;
-    ~EventGuard() {
-        if (e) (void)hipEventDestroy(e);
-    }
-};
-
 // Orders the batch's stream after the caller's stream on entry and the
 // caller's stream after the batch's on every path out, errors included, so
 // the caller never runs ahead of kernels the batch still has in flight.

@@ -61,6 +61,25 @@ struct Geom {
 // directions (a t-neighbour is Lx*Ly*bz positions away instead of Lx*Ly*Lz),
 // which lets an XCD's L2 serve the neighbour re-reads of the operator.
 __device__ __forceinline__ int site_of(const Geom &g, int p) {
+    if (g.parity >= 0 && g.bx > 0) {
+        // one parity in brick order (bx even): positions 2p and 2p + 1 of the
+        // full brick order are x-neighbours in one brick row, x of 2p even
+        const int q0 = 2 * p;
+        const int bvol = g.bx * g.by * g.bz;
+        const int per_brick = bvol * g.L[3];
+        const int brick = q0 / per_brick;
+        int q = q0 - brick * per_brick;
+        const int t = q / bvol;
+        q -= t * bvol;
+        const int nbx = g.L[0] / g.bx, nby = g.L[1] / g.by;
+        const int bxi = brick % nbx, byi = (brick / nbx) % nby, bzi = brick / (nbx * nby);
+        int x = bxi * g.bx + q % g.bx;
+        q /= g.bx;
+        const int y = byi * g.by + q % g.by;
+        const int z = bzi * g.bz + q / g.by;
+        x += ((y + z + t) & 1) ^ g.parity;
+        return x + g.L[0] * (y + g.L[1] * (z + g.L[2] * t));
+    }
     if (g.parity >= 0) {
         // the p-th site of the parity: sites 2p and 2p+1 lie in one x-row
         // (Lx even) and have opposite parities; the row's (y, z, t) decide

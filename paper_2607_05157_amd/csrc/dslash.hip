@@ -35,7 +35,9 @@ __global__ __launch_bounds__(256) void k_dslash(Geom g, const typename S::link *
                                                 typename S::real ch, SpinorPtr<S> in,
                                                 SpinorPtr<S> out, SpinorPtr<S> aux, int N, int NT,
                                                 int SB, double2 *__restrict__ partials,
-                                                int serial_tiles) {
+                                                int serial_tiles, const int *live) {
+    // solver iterations: nothing to do once no RHS is iterating
+    if (live && *live == 0) return;
     const int t0 = serial_tiles > 0 ? 0 : (int)blockIdx.y;
     const int t1 = serial_tiles > 0 ? serial_tiles : t0 + 1;
     dslash_body<S, NC, DAG, EPI, WPS>(g, U, self, cs, ch, in, out, aux, N, NT, SB, partials, t0,
@@ -47,7 +49,9 @@ __global__ __launch_bounds__(256) void k_dslash_march(Geom g, const typename S::
                                                       typename S::real diag, SpinorPtr<S> in,
                                                       SpinorPtr<S> out, SpinorPtr<S> aux, int N,
                                                       int NT, int CB, int TC, int4 B,
-                                                      double2 *__restrict__ partials) {
+                                                      double2 *__restrict__ partials,
+                                                      const int *live) {
+    if (live && *live == 0) return;
     dslash_march_body<S, NC, DAG, EPI, WPS>(g, U, diag, in, out, aux, N, NT, CB, TC, B, partials,
                                        blockIdx.y, xcd_block(blockIdx.x, gridDim.x), gridDim.x);
 }
@@ -63,6 +67,7 @@ template <class S>
 struct HopPtrs {
     SpinorPtr<S> self, in, out, aux;
     typename S::real cs, ch;
+    const int *live;
 };
 
 template <class S, int NC, bool DAG, int EPI>
@@ -75,21 +80,23 @@ static void launch_k(dim3 grid, int threads, hipStream_t stream, const Geom &g,
         if (wps && !march) {
             hipLaunchKernelGGL((k_dslash<S, NC, DAG, EPI, true>), grid, dim3(threads), 0, stream,
                                g, U, h.self, h.cs, h.ch, h.in, h.out, h.aux, N, NT, SB, part,
-                               serial_tiles);
+                               serial_tiles, h.live);
             return;
         }
         if (wps && march) {
             hipLaunchKernelGGL((k_dslash_march<S, NC, DAG, EPI, true>), grid, dim3(threads), 0,
-                               stream, g, U, h.cs, h.in, h.out, h.aux, N, NT, SB, tc, brick, part);
+                               stream, g, U, h.cs, h.in, h.out, h.aux, N, NT, SB, tc, brick, part,
+                               h.live);
             return;
         }
     }
     if (march)
         hipLaunchKernelGGL((k_dslash_march<S, NC, DAG, EPI>), grid, dim3(threads), 0, stream, g,
-                           U, h.cs, h.in, h.out, h.aux, N, NT, SB, tc, brick, part);
+                           U, h.cs, h.in, h.out, h.aux, N, NT, SB, tc, brick, part, h.live);
     else
         hipLaunchKernelGGL((k_dslash<S, NC, DAG, EPI>), grid, dim3(threads), 0, stream, g, U,
-                           h.self, h.cs, h.ch, h.in, h.out, h.aux, N, NT, SB, part, serial_tiles);
+                           h.self, h.cs, h.ch, h.in, h.out, h.aux, N, NT, SB, part, serial_tiles,
+                           h.live);
 }
 
 template <class S, bool DAG, int EPI>
@@ -100,10 +107,15 @@ static int launch_t(const wdt_gauge_s *gf, const HopSpec &hs, const void *in, vo
     Geom g = shaped_geom(gf->lat, sh);
     const int V = g.V;
     if (hs.parity >= 0) {
-        // one parity, plain order (no bricks, no t-march)
+        // one parity: plain or brick order, no t-march
         g = gf->lat.geom();
         g.parity = hs.parity;
         g.nsites = V / 2;
+        if (sh.parity_brick.x > 0) {
+            g.bx = sh.parity_brick.x;
+            g.by = sh.parity_brick.y;
+            g.bz = sh.parity_brick.z;
+        }
         sh.tc = 0;
     }
     // one site per wavefront: 64 lanes per site, four sites per block
@@ -119,6 +131,7 @@ static int launch_t(const wdt_gauge_s *gf, const HopSpec &hs, const void *in, vo
     h.aux = make_spinor<S>(const_cast<void *>(aux), V, N);
     h.cs = (typename S::real)hs.cs;
     h.ch = (typename S::real)hs.ch;
+    h.live = hs.live;
     const int prec = prec_of<S>();
     static const char *names[3] = {"dslash_fp64", "dslash_fp32", "dslash_fp16"};
     // algorithmic bytes: in, out, a separate self, the epilogue's vector, links once

@@ -54,6 +54,9 @@ struct wdt_gauge_s {
     // of packed halves, so that both parts of u h are single half dot products
     __half2 *U16 = nullptr;
     Workspace ws;
+    // two host-mapped ints (host and device address) for the solvers' loop flag
+    int *live_host = nullptr;
+    int *live_dev = nullptr;
 };
 
 namespace wdt {
@@ -93,6 +96,21 @@ struct ProfScope {
     hipEvent_t stop;
     hipStream_t stream;
 };
+// A position in the timing record, and dropping what was recorded after it
+// (launches that turned out to have nothing to do).
+size_t prof_mark();
+void prof_discard(size_t mark);
+
+// Destroys an event on every path out of a scope.
+struct EventGuard {
+    hipEvent_t e = nullptr;
+    EventGuard() = default;
+    EventGuard(const EventGuard &) = delete;
+    EventGuard &operator=(const EventGuard &) = delete;
+    ~EventGuard() {
+        if (e) (void)hipEventDestroy(e);
+    }
+};
 
 // Launch shape of the (site, rhs) kernels: the RHS batch is cut into tiles
 // of NT right-hand sides (grid.y); blocks of NT*SB threads handle SB sites of
@@ -112,6 +130,7 @@ struct Shape {
                   // per block, G blocks over the units); 0: it sweeps sites
     int4 brick;   // march: column bricks (x, y, z extents; x a multiple of SB)
     int4 sweep_brick;  // sweep in brick order (x, y, z extents) when x > 0
+    int4 parity_brick; // one-parity sweeps: brick order (x extent even) when x > 0
     bool wps;     // operator: one site per wavefront (64 RHS lanes, 4 sites per block)
 };
 Shape site_shape(const wdt_lattice_s &lat, int N, int prec);
@@ -173,6 +192,8 @@ struct HopSpec {
     int parity = -1;
     const void *self = nullptr;
     double cs = 0.0, ch = 1.0;
+    // solver iterations: the launch does nothing when *live == 0 (device flag)
+    const int *live = nullptr;
 };
 int launch_hop(const wdt_gauge_s *g, int prec, int dagger, int epi, const HopSpec &hs,
                const void *in, void *out, const void *aux, int N, double2 *partials,

@@ -272,6 +272,19 @@ __device__ __forceinline__ void scalar_omega_beta_body(RhsState *st, const doubl
     }
 }
 
+// Whether any RHS is still iterating (one block): *live in device memory, for
+// the kernels of the next iteration, and *host in host-mapped memory, for the
+// host loop; both 1 or 0.
+__device__ __forceinline__ void live_body(const RhsState *st, int N, int *live, int *host) {
+    int a = 0;
+    for (int r = threadIdx.x; r < N; r += blockDim.x) a |= st[r].active;
+    const int any = __syncthreads_or(a) ? 1 : 0;
+    if (threadIdx.x == 0) {
+        *live = any;
+        if (host) *host = any;
+    }
+}
+
 // rho = the squared norm in partials slot 0 (the start of an iteration whose
 // shadow vector is the current residual).
 __device__ __forceinline__ void scalar_rho_body(RhsState *st, const double2 *partials, int G,

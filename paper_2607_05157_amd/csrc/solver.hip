@@ -11,7 +11,8 @@
 //   p = r + beta (p - omega v)
 // Per-RHS scalars live on the device; small reduction kernels turn the
 // per-block dot partials into alpha, omega, beta and the convergence flags, so
-// the host only polls the flags every `check_every` iterations.  All sums use
+// the host reads one "still iterating" flag per iteration, one iteration
+// behind the device so the queue never drains.  All sums use
 // a fixed order, so results are bit-reproducible run to run.
 #include <algorithm>
 #include <cmath>
@@ -42,13 +43,24 @@ __global__ void k_scalar_check(RhsState *st, const double2 *partials, int G, int
 __global__ void k_scalar_rho(RhsState *st, const double2 *partials, int G, int N) {
     scalar_rho_body(st, partials, G, N, blockIdx.x);
 }
+__global__ void k_live(const RhsState *st, int N, int *live, int *host) {
+    live_body(st, N, live, host);
+}
+
+// The vector kernels of an iteration return at once when no RHS is iterating
+// (*live == 0): the host learns of convergence one iteration late, and the
+// iteration it has already queued by then costs only its launches.
+#define WDT_LIVE_GUARD \
+    if (live && *live == 0) return;
 
 #define WDT_BLOCK_CTX blockIdx.y, xcd_block(blockIdx.x, gridDim.x), gridDim.x
 
 template <class S>
 __global__ __launch_bounds__(256) void k_update_s(Geom g, int N, int NT, int SB,
                                                   const RhsState *__restrict__ st, SpinorPtr<S> rv,
-                                                  SpinorPtr<S> vv, SpinorPtr<S> sv) {
+                                                  SpinorPtr<S> vv, SpinorPtr<S> sv,
+                                                  const int *live) {
+    WDT_LIVE_GUARD
     update_s_body<S>(g, N, NT, SB, st, rv, vv, sv, WDT_BLOCK_CTX);
 }
 template <class S>
@@ -56,13 +68,17 @@ __global__ __launch_bounds__(256) void k_update_xr(Geom g, int N, int NT, int SB
                                                    const RhsState *__restrict__ st, SpinorPtr<S> xv,
                                                    SpinorPtr<S> pv, SpinorPtr<S> sv,
                                                    SpinorPtr<S> tv, SpinorPtr<S> rv,
-                                                   SpinorPtr<S> rhat, double2 *partials) {
+                                                   SpinorPtr<S> rhat, double2 *partials,
+                                                   const int *live) {
+    WDT_LIVE_GUARD
     update_xr_body<S>(g, N, NT, SB, st, xv, pv, sv, tv, rv, rhat, partials, WDT_BLOCK_CTX);
 }
 template <class S>
 __global__ __launch_bounds__(256) void k_update_p(Geom g, int N, int NT, int SB,
                                                   const RhsState *__restrict__ st, SpinorPtr<S> rv,
-                                                  SpinorPtr<S> pv, SpinorPtr<S> vv) {
+                                                  SpinorPtr<S> pv, SpinorPtr<S> vv,
+                                                  const int *live) {
+    WDT_LIVE_GUARD
     update_p_body<S>(g, N, NT, SB, st, rv, pv, vv, WDT_BLOCK_CTX);
 }
 template <class S>
@@ -70,7 +86,9 @@ __global__ __launch_bounds__(256) void k_update_xrp(Geom g, int N, int NT, int S
                                                     const RhsState *__restrict__ st, SpinorPtr<S> xv,
                                                     SpinorPtr<S> pv, SpinorPtr<S> sv,
                                                     SpinorPtr<S> tv, SpinorPtr<S> rv,
-                                                    SpinorPtr<S> vv, double2 *partials) {
+                                                    SpinorPtr<S> vv, double2 *partials,
+                                                    const int *live) {
+    WDT_LIVE_GUARD
     update_xrp_body<S>(g, N, NT, SB, st, xv, pv, sv, tv, rv, vv, partials, WDT_BLOCK_CTX);
 }
 template <class SS, class SD, bool ADD>
@@ -211,6 +229,34 @@ Shape site_shape(const wdt_lattice_s &lat, int N, int prec) {
         // bricks far smaller than the front gain nothing over the plain order
         if (best_vol * 4 < front) sh.sweep_brick = make_int4(0, 0, 0, 0);
     }
+    // One-parity sweeps (even-odd solvers): a brick slice holds half as many
+    // sites of the parity, so the brick may be twice the front; x extent even.
+    sh.parity_brick = make_int4(0, 0, 0, 0);
+    if (tu.brick > 0) {
+        if (sh.sweep_brick.x > 0 && sh.sweep_brick.x % 2 == 0) sh.parity_brick = sh.sweep_brick;
+    } else if (tu.brick == 0 && sh.wps && lat.even_odd_ok()) {
+        const int64_t front = (int64_t)std::max(1, sh.G / 8) * 4;
+        int64_t best_vol = 0;
+        double best_surface = 1e30;
+        for (int bx = 2; bx <= lat.dims[0]; bx += 2) {
+            if (lat.dims[0] % bx) continue;
+            for (int by = 1; by <= lat.dims[1]; ++by) {
+                if (lat.dims[1] % by) continue;
+                for (int bz = 1; bz <= lat.dims[2]; ++bz) {
+                    if (lat.dims[2] % bz) continue;
+                    const int64_t vol = (int64_t)bx * by * bz;
+                    if (vol > 2 * front) continue;
+                    const double surface = 2.0 / bx + 2.0 / by + 2.0 / bz;
+                    if (vol > best_vol || (vol == best_vol && surface < best_surface)) {
+                        sh.parity_brick = make_int4(bx, by, bz, 0);
+                        best_vol = vol;
+                        best_surface = surface;
+                    }
+                }
+            }
+        }
+        if (best_vol * 2 < front) sh.parity_brick = make_int4(0, 0, 0, 0);
+    }
     // t-marching operator: chunks of tc slices over bricks of columns
     sh.tc = 0;
     sh.brick = make_int4(0, 0, 0, 0);
@@ -316,7 +362,38 @@ struct Bicg {
     RhsState *st;
     double2 *part;
     bool eo = false;  // iterate on the even-site Schur complement
+    int *live = nullptr;            // device flag: some RHS is iterating
+    int *live_host = nullptr;       // two host-mapped slots the iterations write in turn
+    int *live_dev_slots = nullptr;  // the same slots, device address
 };
+
+// Two host-mapped ints per gauge handle for the iteration loop's flag.
+int ensure_live_slots(wdt_gauge_s *g) {
+    if (g->live_host) return WDT_OK;
+    void *h = nullptr;
+    if (hipHostMalloc(&h, 256, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(WDT_ENOMEM, "host-mapped flag allocation failed");
+    }
+    void *d = nullptr;
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(h);
+        return set_error(WDT_EHIP, "host-mapped flag: no device address");
+    }
+    g->live_host = (int *)h;
+    g->live_dev = (int *)d;
+    return WDT_OK;
+}
+
+// Binds the flag slots: the device flag at `dev_flag` (workspace memory).
+int bind_live(Bicg &B, int *dev_flag) {
+    WDT_TRY(ensure_live_slots(B.g));
+    B.live = dev_flag;
+    B.live_host = B.g->live_host;
+    B.live_dev_slots = B.g->live_dev;
+    return WDT_OK;
+}
 
 // Even-odd preconditioning: on when every extent is even, unless the tuner
 // switches it off.
@@ -343,19 +420,27 @@ Geom parity_geom(const wdt_lattice_s &lat, int parity) {
 // Vectors keep the full-lattice layout; the iteration touches even sites only
 // and uses the odd sites of its output vector as scratch for H_oe x_e.
 int apply_op(Bicg &B, int prec, int epi, const void *in, void *out, const void *aux) {
-    if (!B.eo)
-        return launch_dslash(B.g, B.m0, prec, 0, epi, in, out, aux, B.N, B.part, B.sh, B.stream);
     const double a = 4.0 + B.m0;
+    if (!B.eo) {
+        HopSpec h;
+        h.self = in;
+        h.cs = a;
+        h.ch = -0.5;
+        h.live = B.live;
+        return launch_hop(B.g, prec, 0, epi, h, in, out, aux, B.N, B.part, B.sh, B.stream);
+    }
     HopSpec h1;
     h1.parity = 1;
     h1.cs = 0.0;
     h1.ch = 1.0;
+    h1.live = B.live;
     WDT_TRY(launch_hop(B.g, prec, 0, EPI_NONE, h1, in, out, nullptr, B.N, nullptr, B.sh, B.stream));
     HopSpec h2;
     h2.parity = 0;
     h2.self = in;
     h2.cs = a;
     h2.ch = -1.0 / (4.0 * a);
+    h2.live = B.live;
     return launch_hop(B.g, prec, 0, epi, h2, out, out, aux, B.N, B.part, B.sh, B.stream);
 }
 
@@ -384,10 +469,17 @@ int schur_odd(Bicg &B, int prec, const void *b, void *x) {
 // Runs BiCGStab iterations in storage S until every RHS is inactive or
 // `max_iter` is reached.  x, r, rhat, p, v, s, t are S-format vectors; the
 // state must have been initialised (rho, active, tolerances).
+//
+// Convergence is checked after every iteration without stalling the device:
+// each iteration ends with a one-block kernel that writes "some RHS is still
+// iterating" to a device flag and to a host-mapped slot.  The host queues
+// iteration k, then waits for the end of iteration k - 1 and reads its slot;
+// if nothing was left to do, iteration k's kernels find the device flag clear
+// and return at once, and the loop ends.  `iters_done` counts the iterations
+// that ran.
 template <class S>
 int bicgstab_iterate(Bicg &B, int prec, void *x, void *r, void *rhat, void *p, void *v, void *s,
-                     void *t, int max_iter, int check_every, std::vector<RhsState> &host_st,
-                     int *iters_done) {
+                     void *t, int max_iter, int *iters_done) {
     const int V = B.V, N = B.N;
     const Shape &sh = B.sh;
     int it = 0;
@@ -400,14 +492,19 @@ int bicgstab_iterate(Bicg &B, int prec, void *x, void *r, void *rhat, void *p, v
     static const char *nm_xrp[3] = {"update_xrp_fp64", "update_xrp_fp32", "update_xrp_fp16"};
     // the inner solves of the mixed solver take the fused end of iteration
     constexpr bool fused = !std::is_same<S, F64>::value;
+    EventGuard ev[2];
+    for (auto &e : ev) WDT_HIP(hipEventCreateWithFlags(&e.e, hipEventDisableTiming));
+    hipLaunchKernelGGL(k_live, dim3(1), dim3(256), 0, B.stream, B.st, N, B.live, (int *)nullptr);
+    volatile int *slot = B.live_host;
     while (it < max_iter) {
+        const size_t mark = prof_mark();
         WDT_TRY(apply_op(B, prec, EPI_DOT_AUX, p, v, rhat));
         hipLaunchKernelGGL(k_scalar_alpha, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.G, N);
         {
             ProfScope pr(nm_s[prec], 3 * vb, B.stream);
             hipLaunchKernelGGL((k_update_s<S>), B.grid, dim3(sh.threads), 0, B.stream, B.geo, N, B.NT,
-                               sh.SB, B.st, sp<S>(r, V, N), sp<S>(v, V, N),
-                               sp<S>(s, V, N));
+                               sh.SB, B.st, sp<S>(r, V, N), sp<S>(v, V, N), sp<S>(s, V, N),
+                               (const int *)B.live);
         }
         if constexpr (fused) {
             WDT_TRY(apply_op(B, prec, EPI_DOT_TSR, s, t, rhat));
@@ -418,47 +515,43 @@ int bicgstab_iterate(Bicg &B, int prec, void *x, void *r, void *rhat, void *p, v
                 hipLaunchKernelGGL((k_update_xrp<S>), B.grid, dim3(sh.threads), 0, B.stream, B.geo,
                                    N, B.NT, sh.SB, B.st, sp<S>(x, V, N), sp<S>(p, V, N),
                                    sp<S>(s, V, N), sp<S>(t, V, N), sp<S>(r, V, N),
-                                   sp<S>(v, V, N), B.part);
+                                   sp<S>(v, V, N), B.part, (const int *)B.live);
             }
             hipLaunchKernelGGL(k_scalar_check, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.Gv,
                                N);
-            WDT_HIP(hipGetLastError());
-            ++it;
-            if (it % check_every == 0 || it == max_iter) {
-                WDT_HIP(hipMemcpyAsync(host_st.data(), B.st, sizeof(RhsState) * N,
-                                       hipMemcpyDeviceToHost, B.stream));
-                WDT_HIP(hipStreamSynchronize(B.stream));
-                bool any = false;
-                for (int k = 0; k < N; ++k) any = any || host_st[k].active;
-                if (!any) break;
+        } else {
+            WDT_TRY(apply_op(B, prec, EPI_DOT_TS, s, t, nullptr));
+            hipLaunchKernelGGL(k_scalar_omega, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.G,
+                               N);
+            {
+                ProfScope pr(nm_xr[prec], 7 * vb, B.stream);
+                hipLaunchKernelGGL((k_update_xr<S>), B.grid, dim3(sh.threads), 0, B.stream, B.geo,
+                                   N, B.NT, sh.SB, B.st, sp<S>(x, V, N), sp<S>(p, V, N),
+                                   sp<S>(s, V, N), sp<S>(t, V, N), sp<S>(r, V, N),
+                                   sp<S>(rhat, V, N), B.part, (const int *)B.live);
             }
-            continue;
+            hipLaunchKernelGGL(k_scalar_beta, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.Gv,
+                               N);
+            {
+                ProfScope pr(nm_p[prec], 4 * vb, B.stream);
+                hipLaunchKernelGGL((k_update_p<S>), B.grid, dim3(sh.threads), 0, B.stream, B.geo,
+                                   N, B.NT, sh.SB, B.st, sp<S>(r, V, N), sp<S>(p, V, N),
+                                   sp<S>(v, V, N), (const int *)B.live);
+            }
         }
-        WDT_TRY(apply_op(B, prec, EPI_DOT_TS, s, t, nullptr));
-        hipLaunchKernelGGL(k_scalar_omega, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.G, N);
-        {
-            ProfScope pr(nm_xr[prec], 7 * vb, B.stream);
-            hipLaunchKernelGGL((k_update_xr<S>), B.grid, dim3(sh.threads), 0, B.stream, B.geo, N, B.NT,
-                               sh.SB, B.st, sp<S>(x, V, N), sp<S>(p, V, N),
-                               sp<S>(s, V, N), sp<S>(t, V, N), sp<S>(r, V, N), sp<S>(rhat, V, N),
-                               B.part);
-        }
-        hipLaunchKernelGGL(k_scalar_beta, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.Gv, N);
-        {
-            ProfScope pr(nm_p[prec], 4 * vb, B.stream);
-            hipLaunchKernelGGL((k_update_p<S>), B.grid, dim3(sh.threads), 0, B.stream, B.geo, N, B.NT,
-                               sh.SB, B.st, sp<S>(r, V, N), sp<S>(p, V, N),
-                               sp<S>(v, V, N));
-        }
+        hipLaunchKernelGGL(k_live, dim3(1), dim3(256), 0, B.stream, B.st, N, B.live,
+                           B.live_dev_slots + (it & 1));
         WDT_HIP(hipGetLastError());
+        WDT_HIP(hipEventRecord(ev[it & 1].e, B.stream));
         ++it;
-        if (it % check_every == 0 || it == max_iter) {
-            WDT_HIP(hipMemcpyAsync(host_st.data(), B.st, sizeof(RhsState) * N,
-                                   hipMemcpyDeviceToHost, B.stream));
-            WDT_HIP(hipStreamSynchronize(B.stream));
-            bool any = false;
-            for (int k = 0; k < N; ++k) any = any || host_st[k].active;
-            if (!any) break;
+        if (it >= 2) {
+            // iteration it - 2 (slot it & 1) has ended: was the one just queued needed?
+            WDT_HIP(hipEventSynchronize(ev[it & 1].e));
+            if (slot[it & 1] == 0) {
+                prof_discard(mark);
+                --it;
+                break;
+            }
         }
     }
     *iters_done = it;
@@ -479,7 +572,8 @@ static int solve_fp64(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
     const size_t st_bytes = ((sizeof(RhsState) * N + 255) / 256) * 256;
     const size_t part_off = 6 * vb;
     const size_t st_off = part_off + ((part_bytes + 255) / 256) * 256;
-    WDT_TRY(ensure_ws(g, st_off + st_bytes));
+    const size_t live_off = st_off + st_bytes;
+    WDT_TRY(ensure_ws(g, live_off + 256));
     char *base = (char *)g->ws.ptr;
     void *r = base, *rhat = base + vb, *p = base + 2 * vb, *v = base + 3 * vb, *s = base + 4 * vb,
          *t = base + 5 * vb;
@@ -487,11 +581,11 @@ static int solve_fp64(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
            (RhsState *)(base + st_off), (double2 *)(base + part_off)};
     B.eo = use_even_odd(g->lat);
     if (B.eo) B.geo = parity_geom(g->lat, 0);
+    WDT_TRY(bind_live(B, (int *)(base + live_off)));
     WDT_HIP(hipMemsetAsync(B.st, 0, sizeof(RhsState) * N, stream));
     if (!P.x0_is_guess) WDT_HIP(hipMemsetAsync(x, 0, vb, stream));
     std::vector<RhsState> hs(N);
     std::vector<int> total_it(N, 0), restarts(N, 0);
-    const int check = P.check_every > 0 ? P.check_every : 5;
     int budget = P.max_iter;
     int rc = WDT_OK;
     for (int round = 0;; ++round) {
@@ -528,7 +622,7 @@ static int solve_fp64(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
         std::vector<int> before(N);
         for (int k = 0; k < N; ++k) before[k] = hs[k].iters;
         int done = 0;
-        WDT_TRY(bicgstab_iterate<F64>(B, WDT_FP64, x, r, rhat, p, v, s, t, budget, check, hs, &done));
+        WDT_TRY(bicgstab_iterate<F64>(B, WDT_FP64, x, r, rhat, p, v, s, t, budget, &done));
         if (B.eo) WDT_TRY(schur_odd(B, WDT_FP64, b, x));
         WDT_HIP(hipMemcpyAsync(hs.data(), B.st, sizeof(RhsState) * N, hipMemcpyDeviceToHost, stream));
         WDT_HIP(hipStreamSynchronize(stream));
@@ -554,7 +648,8 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
     const size_t st_off = part_off + ((part_bytes + 255) / 256) * 256;
     const size_t mask_off = st_off + st_bytes;
     const size_t fac_off = mask_off + ((sizeof(int) * N + 255) / 256) * 256;
-    WDT_TRY(ensure_ws(g, fac_off + 2 * ((sizeof(double) * N + 255) / 256) * 256));
+    const size_t live_off = fac_off + 2 * ((sizeof(double) * N + 255) / 256) * 256;
+    WDT_TRY(ensure_ws(g, live_off + 256));
     char *base = (char *)g->ws.ptr;
     void *r64 = base;
     void *lo[7];
@@ -569,12 +664,12 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
            (RhsState *)(base + st_off), (double2 *)(base + part_off)};
     B.eo = use_even_odd(g->lat);
     if (B.eo) B.geo = parity_geom(g->lat, 0);
+    WDT_TRY(bind_live(B, (int *)(base + live_off)));
     const dim3 grid(sh.Gv, sh.tiles);
     if (!P.x0_is_guess) WDT_HIP(hipMemsetAsync(x, 0, vb64, stream));
     std::vector<RhsState> hs(N);
     std::vector<int> hmask(N);
     std::vector<int> total_it(N, 0), outer(N, 0);
-    const int check = P.check_every > 0 ? P.check_every : 5;
     const double inner_tol = P.inner_tol > 0 ? P.inner_tol : 1e-2;
     const int max_outer = P.max_outer > 0 ? P.max_outer : 30;
     int budget = P.max_iter;
@@ -644,7 +739,7 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
         WDT_HIP(hipStreamSynchronize(stream));
         for (int k = 0; k < N; ++k) before[k] = hs[k].iters;
         int done = 0;
-        WDT_TRY(bicgstab_iterate<S>(B, prec, e, rS, rhat, p, v, s, t, budget, check, hs, &done));
+        WDT_TRY(bicgstab_iterate<S>(B, prec, e, rS, rhat, p, v, s, t, budget, &done));
         if (B.eo) WDT_TRY(schur_odd(B, prec, rS, e));
         WDT_HIP(hipMemcpyAsync(hs.data(), B.st, sizeof(RhsState) * N, hipMemcpyDeviceToHost, stream));
         WDT_HIP(hipStreamSynchronize(stream));
