@@ -145,12 +145,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--inner-tol", type=float, default=0.02)
+    ap.add_argument("--inner-tol", type=float, default=0.005)
     ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the trace estimate "
-              "shards by colour batch with no communication, see DESIGN.md", file=sys.stderr)
+              "shards by colour batch with no communication", file=sys.stderr)
         return 2
 
     import numpy as np

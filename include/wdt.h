@@ -169,7 +169,9 @@ typedef struct {
     double tol;          /* target true relative residual, e.g. 1e-10 */
     int32_t max_iter;    /* cap on (inner) BiCGStab iterations per RHS */
     int32_t prec;        /* WDT_FP64, WDT_FP32 or WDT_FP16 */
-    double inner_tol;    /* relative residual reduction per inner solve */
+    double inner_tol;    /* relative residual reduction per inner solve
+                            (<= 0: 0.005); the last solve of a RHS stops
+                            earlier if that already meets tol */
     int32_t max_outer;   /* cap on defect-correction steps */
     int32_t x0_is_guess; /* 1: dev_x holds a starting guess */
     int32_t check_every; /* wdt_batch_solve: iterations between convergence

@@ -184,7 +184,7 @@ __global__ __launch_bounds__(256) void kb_copy(const SysDesc *sys, int nsys, int
 
 __global__ void kb_init(const SysDesc *sys, int nsys, RhsState *st, double tol) {
     WDT_RHS_CTX
-    init_state_body(s0, d.part, d.G, d.N, tol, nullptr, r);
+    init_state_body(s0, d.part, d.G, d.N, tol, nullptr, nullptr, nullptr, r);
 }
 __global__ void kb_alpha(const SysDesc *sys, int nsys, RhsState *st) {
     WDT_RHS_CTX

@@ -49,15 +49,19 @@ __device__ __forceinline__ double2 block_sum(const double2 *__restrict__ partial
 
 // After r = b - D x: rr = ||r||^2, bb = ||b||^2; start the recurrence with
 // rhat = r.  `bb_ref` (optional) supplies the norm the tolerance refers to.
+// tolr (may be null): per-RHS tolerances in place of tol; bbv (may be null):
+// per-RHS ||b||^2 in place of partials slot 1.
 __device__ __forceinline__ void init_state_body(RhsState *st, const double2 *partials, int G,
-                                                int N, double tol, const int *mask, int r) {
+                                                int N, double tol, const int *mask,
+                                                const double *tolr, const double *bbv, int r) {
     const double2 rr = block_sum(partials, 0, G, N, r);
-    const double2 bb = block_sum(partials, 1, G, N, r);
+    const double2 bb = bbv ? make_double2(bbv[r], 0.0) : block_sum(partials, 1, G, N, r);
     if (threadIdx.x == 0) {
         RhsState s = st[r];
         s.rr = rr.x;
         s.bb = bb.x;
-        s.tol2 = tol * tol;
+        const double tl = tolr ? tolr[r] : tol;
+        s.tol2 = tl * tl;
         s.rho = make_double2(rr.x, 0.0);
         s.alpha = make_double2(0, 0);
         s.omega = make_double2(0, 0);
@@ -360,15 +364,43 @@ __device__ __forceinline__ void update_xrp_body(const Geom &g, int N, int NT, in
     }
 }
 
+// partials slot 0 of block Lb: the block's ||src||^2 per RHS.
+template <class S>
+__device__ __forceinline__ void norm_body(const Geom &g, int N, int NT, int SB, SpinorPtr<S> src,
+                                          double2 *__restrict__ partials, int tile, int lb,
+                                          int gb) {
+    __shared__ double red[256];
+    double d0 = 0;
+    SITE_LOOP_BEGIN_AT(tile, lb, gb)
+    cplx<Rl<S>> a[12];
+    load_site<S>(src, s, r, a);
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        d0 += (double)a[k].re * (double)a[k].re + (double)a[k].im * (double)a[k].im;
+    SITE_LOOP_END
+    red[tid] = d0;
+    __syncthreads();
+    if (ry == 0 && r < N) {
+        double s0 = red[rl];
+        for (int y = 1; y < SB; ++y) s0 += red[y * NT + rl];
+        partials[(size_t)Lb * N + r] = make_double2(s0, 0.0);
+    }
+}
+
 // dst = f[r] * src converted (dst += f[r] * src when ADD); f = nullptr: 1.
 // The product is formed in FP64 before the conversion, so a residual can be
 // brought to unit norm on its way into low precision and the correction
-// scaled back on its way out.
+// scaled back on its way out.  partials (may be null): slots 0 and 1 of
+// block Lb both get the block's ||dst||^2 (of the value before rounding to
+// the storage precision).
 template <class SS, class SD, bool ADD>
 __device__ __forceinline__ void convert_body(const Geom &g, int N, int NT, int SB,
                                              SpinorPtr<SS> src, SpinorPtr<SD> dst,
-                                             const double *__restrict__ f, int tile, int lb,
+                                             const double *__restrict__ f,
+                                             double2 *__restrict__ partials, int tile, int lb,
                                              int gb) {
+    __shared__ double red[256];
+    double d0 = 0;
     SITE_LOOP_BEGIN_AT(tile, lb, gb)
     const double fr = f ? f[r] : 1.0;
     cplx<Rl<SS>> a[12];
@@ -386,8 +418,23 @@ __device__ __forceinline__ void convert_body(const Geom &g, int N, int NT, int S
         for (int k = 0; k < 12; ++k)
             b[k] = {(Rl<SD>)(fr * (double)a[k].re), (Rl<SD>)(fr * (double)a[k].im)};
     }
+    if (partials) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            d0 += (double)b[k].re * (double)b[k].re + (double)b[k].im * (double)b[k].im;
+    }
     store_site<SD>(dst, s, r, b);
     SITE_LOOP_END
+    if (partials) {
+        red[tid] = d0;
+        __syncthreads();
+        if (ry == 0 && r < N) {
+            double s0 = red[rl];
+            for (int y = 1; y < SB; ++y) s0 += red[y * NT + rl];
+            partials[(size_t)Lb * N + r] = make_double2(s0, 0.0);
+            partials[((size_t)Gb + Lb) * N + r] = make_double2(s0, 0.0);
+        }
+    }
 }
 
 
@@ -424,6 +471,9 @@ __device__ __forceinline__ void pin_elems(E (&e)[12]) {
 
 // Schedule per precision: one direction (two spinors, two links) in flight.
 template <class S> struct OpPin { static constexpr int value = 1; };
+#ifdef WDT_OP_PIN_F16
+template <> struct OpPin<F16> { static constexpr int value = WDT_OP_PIN_F16; };
+#endif
 
 // Non-temporal output stores keep the operator's output from evicting input
 // lines that neighbouring sites still have to re-read from L2.
@@ -736,10 +786,12 @@ __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::lin
             cplx<R> acc[12];
 #pragma unroll
             for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
-            hop_pair<0, DAG, PIN, NC, S>(g, U, in, s, nb, r, acc);
-            hop_pair<1, DAG, PIN, NC, S>(g, U, in, s, nb, r, acc);
-            hop_pair<2, DAG, PIN, NC, S>(g, U, in, s, nb, r, acc);
-            hop_pair<3, DAG, PIN, NC, S>(g, U, in, s, nb, r, acc);
+            // PIN 3: the accumulator is pinned after every second direction
+            constexpr int PA = PIN == 3 ? 0 : PIN, PB = PIN == 3 ? 1 : PIN;
+            hop_pair<0, DAG, PA, NC, S>(g, U, in, s, nb, r, acc);
+            hop_pair<1, DAG, PB, NC, S>(g, U, in, s, nb, r, acc);
+            hop_pair<2, DAG, PA, NC, S>(g, U, in, s, nb, r, acc);
+            hop_pair<3, DAG, PB, NC, S>(g, U, in, s, nb, r, acc);
             cplx<R> c[12];
             if (cs != R(0)) {
                 load_site<S, NC>(self, s, r, c);

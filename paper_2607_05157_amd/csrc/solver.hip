@@ -22,8 +22,8 @@
 namespace wdt {
 
 __global__ void k_init_state(RhsState *st, const double2 *partials, int G, int N, double tol,
-                             const int *mask) {
-    init_state_body(st, partials, G, N, tol, mask, blockIdx.x);
+                             const int *mask, const double *tolr, const double *bbv) {
+    init_state_body(st, partials, G, N, tol, mask, tolr, bbv, blockIdx.x);
 }
 __global__ void k_scalar_alpha(RhsState *st, const double2 *partials, int G, int N) {
     scalar_alpha_body(st, partials, G, N, blockIdx.x);
@@ -45,6 +45,11 @@ __global__ void k_scalar_rho(RhsState *st, const double2 *partials, int G, int N
 }
 __global__ void k_live(const RhsState *st, int N, int *live, int *host) {
     live_body(st, N, live, host);
+}
+// out[r] = the sum of partials slot 0 over G blocks
+__global__ void k_sum_to(double *out, const double2 *partials, int G, int N) {
+    const double2 v = block_sum(partials, 0, G, N, blockIdx.x);
+    if (threadIdx.x == 0) out[blockIdx.x] = v.x;
 }
 
 // The vector kernels of an iteration return at once when no RHS is iterating
@@ -91,11 +96,17 @@ __global__ __launch_bounds__(256) void k_update_xrp(Geom g, int N, int NT, int S
     WDT_LIVE_GUARD
     update_xrp_body<S>(g, N, NT, SB, st, xv, pv, sv, tv, rv, vv, partials, WDT_BLOCK_CTX);
 }
+template <class S>
+__global__ __launch_bounds__(256) void k_norm(Geom g, int N, int NT, int SB, SpinorPtr<S> src,
+                                              double2 *__restrict__ partials) {
+    norm_body<S>(g, N, NT, SB, src, partials, WDT_BLOCK_CTX);
+}
 template <class SS, class SD, bool ADD>
 __global__ __launch_bounds__(256) void k_convert(Geom g, int N, int NT, int SB,
                                                  SpinorPtr<SS> src, SpinorPtr<SD> dst,
-                                                 const double *__restrict__ f) {
-    convert_body<SS, SD, ADD>(g, N, NT, SB, src, dst, f, WDT_BLOCK_CTX);
+                                                 const double *__restrict__ f,
+                                                 double2 *__restrict__ partials) {
+    convert_body<SS, SD, ADD>(g, N, NT, SB, src, dst, f, partials, WDT_BLOCK_CTX);
 }
 
 // ---------------------------------------------------------------------------
@@ -592,7 +603,8 @@ static int solve_fp64(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
         // r = b - D x (true residual), rhat = r
         WDT_TRY(launch_dslash(g, m0, WDT_FP64, 0, EPI_RESID, x, r, b, N, B.part, sh, stream));
         hipLaunchKernelGGL(k_init_state, dim3(N), dim3(256), 0, stream, B.st, B.part, sh.G, N,
-                           P.tol, (const int *)nullptr);
+                           P.tol, (const int *)nullptr, (const double *)nullptr,
+                           (const double *)nullptr);
         if (B.eo) {
             // the correction solves M e_e = r_e + H_eo r_o / (2a); rho = its norm
             WDT_TRY(schur_rhs(B, WDT_FP64, r));
@@ -643,12 +655,13 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
     const size_t vbl = ((spinor_bytes(V, N, prec) + 255) / 256) * 256;
     const size_t part_bytes = (size_t)3 * std::max(sh.G, sh.Gv) * N * sizeof(double2);
     const size_t st_bytes = ((sizeof(RhsState) * N + 255) / 256) * 256;
+    const size_t nrow = ((N + 31) / 32) * 32;  // per-RHS array stride (doubles)
     const size_t low_off = vb64;
     const size_t part_off = low_off + 7 * vbl;
     const size_t st_off = part_off + ((part_bytes + 255) / 256) * 256;
     const size_t mask_off = st_off + st_bytes;
     const size_t fac_off = mask_off + ((sizeof(int) * N + 255) / 256) * 256;
-    const size_t live_off = fac_off + 2 * ((sizeof(double) * N + 255) / 256) * 256;
+    const size_t live_off = fac_off + ((4 * nrow * sizeof(double) + 255) / 256) * 256;
     WDT_TRY(ensure_ws(g, live_off + 256));
     char *base = (char *)g->ws.ptr;
     void *r64 = base;
@@ -656,30 +669,55 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
     for (int i = 0; i < 7; ++i) lo[i] = base + low_off + i * vbl;
     void *rS = lo[0], *rhat = lo[1], *p = lo[2], *v = lo[3], *s = lo[4], *t = lo[5], *e = lo[6];
     int *mask = (int *)(base + mask_off);
-    // per RHS: 1/||r|| into the inner solve, ||r|| back out
+    // per RHS: 1/||r|| into the inner solve, ||r|| back out, the inner
+    // tolerance, ||b||^2 (even-odd)
     double *fin = (double *)(base + fac_off);
-    double *fout = fin + ((N + 31) / 32) * 32;
-    std::vector<double> hfac(2 * (size_t)((N + 31) / 32) * 32, 0.0);
+    double *fout = fin + nrow, *tolr = fin + 2 * nrow, *bbv = fin + 3 * nrow;
+    std::vector<double> hfac(3 * nrow, 0.0);
     Bicg B{g, m0, N, V, sh, geo, NT, dim3(sh.Gv, sh.tiles), stream,
            (RhsState *)(base + st_off), (double2 *)(base + part_off)};
     B.eo = use_even_odd(g->lat);
     if (B.eo) B.geo = parity_geom(g->lat, 0);
     WDT_TRY(bind_live(B, (int *)(base + live_off)));
     const dim3 grid(sh.Gv, sh.tiles);
+    // the sites the defect correction updates: all, or the even ones
+    const Geom &ug = B.geo;
+    const double a = 4.0 + m0;
     if (!P.x0_is_guess) WDT_HIP(hipMemsetAsync(x, 0, vb64, stream));
     std::vector<RhsState> hs(N);
     std::vector<int> hmask(N);
     std::vector<int> total_it(N, 0), outer(N, 0);
-    const double inner_tol = P.inner_tol > 0 ? P.inner_tol : 1e-2;
+    const double inner_tol = P.inner_tol > 0 ? P.inner_tol : 5e-3;
     const int max_outer = P.max_outer > 0 ? P.max_outer : 30;
     int budget = P.max_iter;
     int rc = WDT_OK;
     WDT_HIP(hipMemsetAsync(B.st, 0, sizeof(RhsState) * N, stream));
+    if (B.eo) {
+        // Even-odd: x_o is kept equal to (b_o + H_oe x_e / 2) / a in FP64, so
+        // the odd rows of the residual vanish and b - D x is the even-site
+        // residual r_e = b_e - a x_e + H_eo x_o / 2 of one one-parity
+        // launch; the inner solves take the Schur system M e_e = r_e, and
+        // only x_e is corrected.  ||b||^2 over the whole lattice, once:
+        hipLaunchKernelGGL((k_norm<F64>), grid, dim3(sh.threads), 0, stream, geo, N, NT, sh.SB,
+                           sp<F64>(const_cast<void *>(b), V, N), B.part);
+        hipLaunchKernelGGL(k_sum_to, dim3(N), dim3(256), 0, stream, bbv, B.part, sh.Gv, N);
+        WDT_TRY(schur_odd(B, WDT_FP64, b, x));
+    }
     for (int o = 0;; ++o) {
         // FP64 true residual r64 = b - D x
-        WDT_TRY(launch_dslash(g, m0, WDT_FP64, 0, EPI_RESID, x, r64, b, N, B.part, sh, stream));
+        if (B.eo) {
+            HopSpec h;
+            h.parity = 0;
+            h.self = x;
+            h.cs = a;
+            h.ch = -0.5;
+            WDT_TRY(launch_hop(g, WDT_FP64, 0, EPI_RESID, h, x, r64, b, N, B.part, sh, stream));
+        } else {
+            WDT_TRY(launch_dslash(g, m0, WDT_FP64, 0, EPI_RESID, x, r64, b, N, B.part, sh, stream));
+        }
         hipLaunchKernelGGL(k_init_state, dim3(N), dim3(256), 0, stream, B.st, B.part, sh.G, N,
-                           P.tol, (const int *)nullptr);
+                           P.tol, (const int *)nullptr, (const double *)nullptr,
+                           (const double *)(B.eo ? bbv : nullptr));
         WDT_HIP(hipMemcpyAsync(hs.data(), B.st, sizeof(RhsState) * N, hipMemcpyDeviceToHost, stream));
         WDT_HIP(hipStreamSynchronize(stream));
         bool any = false;
@@ -704,33 +742,40 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
         WDT_HIP(hipMemcpyAsync(mask, hmask.data(), sizeof(int) * N, hipMemcpyHostToDevice, stream));
         // The inner system is D e = r / ||r|| (unit norm whatever the scale of
         // b, so the low-precision data stays far from under- and overflow as
-        // the residual falls); x += ||r|| e afterwards.
-        const size_t half = hfac.size() / 2;
+        // the residual falls); x += ||r|| e afterwards.  Its tolerance is
+        // inner_tol, or what is left to reach tol if that is less demanding
+        // (the last correction of a RHS stops as soon as it suffices).
         for (int k = 0; k < N; ++k) {
             const double nr = std::sqrt(hs[k].rr);
             const bool ok = hmask[k] && nr > 0 && std::isfinite(nr);
             hfac[k] = ok ? 1.0 / nr : 0.0;
-            hfac[half + k] = ok ? nr : 0.0;
+            hfac[nrow + k] = ok ? nr : 0.0;
+            const double left = ok ? 0.5 * P.tol * std::sqrt(hs[k].bb) / nr : 0.0;
+            hfac[2 * nrow + k] = std::min(0.5, std::max(inner_tol, left));
         }
         WDT_HIP(hipMemcpyAsync(fin, hfac.data(), sizeof(double) * hfac.size(), hipMemcpyHostToDevice,
                                stream));
-        // inner system D e = r (low precision), e = 0, rhat = r
-        hipLaunchKernelGGL((k_convert<F64, S, false>), grid, dim3(sh.threads), 0, stream, geo, N, NT,
-                           sh.SB, sp<F64>(r64, V, N), sp<S>(rS, V, N), (const double *)fin);
         WDT_HIP(hipMemsetAsync(e, 0, vbl, stream));
         if (B.eo) {
-            // even-odd: the inner system is M e_e = rS_e + H_eo rS_o / (2a); the
-            // odd sites of rS keep rS_o for the reconstruction of e_o
-            WDT_TRY(schur_rhs(B, prec, rS));
-            hipLaunchKernelGGL(k_init_state, dim3(N), dim3(256), 0, stream, B.st, B.part, sh.G, N,
-                               inner_tol, (const int *)mask);
+            // rS_e = r_e / ||r|| and its norm for the inner state
+            hipLaunchKernelGGL((k_convert<F64, S, false>), grid, dim3(sh.threads), 0, stream, ug,
+                               N, NT, sh.SB, sp<F64>(r64, V, N), sp<S>(rS, V, N),
+                               (const double *)fin, B.part);
+            hipLaunchKernelGGL(k_init_state, dim3(N), dim3(256), 0, stream, B.st, B.part, sh.Gv,
+                               N, inner_tol, (const int *)mask, (const double *)tolr,
+                               (const double *)nullptr);
             WDT_HIP(hipMemcpyAsync(rhat, rS, spinor_bytes(V, N, prec), hipMemcpyDeviceToDevice,
                                    stream));
         } else {
+            // inner system D e = r (low precision), e = 0, rhat = r
+            hipLaunchKernelGGL((k_convert<F64, S, false>), grid, dim3(sh.threads), 0, stream, geo,
+                               N, NT, sh.SB, sp<F64>(r64, V, N), sp<S>(rS, V, N),
+                               (const double *)fin, (double2 *)nullptr);
             // ||r||^2 in the stored precision: residual of e = 0 against rS
             WDT_TRY(launch_dslash(g, m0, prec, 0, EPI_RESID, e, rhat, rS, N, B.part, sh, stream));
             hipLaunchKernelGGL(k_init_state, dim3(N), dim3(256), 0, stream, B.st, B.part, sh.G, N,
-                               inner_tol, (const int *)mask);
+                               inner_tol, (const int *)mask, (const double *)tolr,
+                               (const double *)nullptr);
             WDT_HIP(hipMemcpyAsync(rS, rhat, spinor_bytes(V, N, prec), hipMemcpyDeviceToDevice,
                                    stream));
         }
@@ -740,15 +785,16 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
         for (int k = 0; k < N; ++k) before[k] = hs[k].iters;
         int done = 0;
         WDT_TRY(bicgstab_iterate<S>(B, prec, e, rS, rhat, p, v, s, t, budget, &done));
-        if (B.eo) WDT_TRY(schur_odd(B, prec, rS, e));
         WDT_HIP(hipMemcpyAsync(hs.data(), B.st, sizeof(RhsState) * N, hipMemcpyDeviceToHost, stream));
         WDT_HIP(hipStreamSynchronize(stream));
         for (int k = 0; k < N; ++k) total_it[k] += hs[k].iters - before[k];
         budget -= done;
-        // x += e
-        hipLaunchKernelGGL((k_convert<S, F64, true>), grid, dim3(sh.threads), 0, stream, geo, N, NT,
-                           sh.SB, sp<S>(e, V, N), sp<F64>(x, V, N), (const double *)fout);
+        // x += ||r|| e (even-odd: x_e, then x_o from b_o and x_e)
+        hipLaunchKernelGGL((k_convert<S, F64, true>), grid, dim3(sh.threads), 0, stream, ug, N, NT,
+                           sh.SB, sp<S>(e, V, N), sp<F64>(x, V, N), (const double *)fout,
+                           (double2 *)nullptr);
         WDT_HIP(hipGetLastError());
+        if (B.eo) WDT_TRY(schur_odd(B, WDT_FP64, b, x));
     }
     (void)rc;
 }

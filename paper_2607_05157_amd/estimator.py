@@ -61,7 +61,7 @@ def colours_on_slice(dims, n_c, sigma, t0):
 
 
 def probing_loop(gauge, lat, m0, n_c, sigma, t0, seeds, n_rhs=48, dilution=12, tol=1e-10,
-                 prec=wdt.FP16, spin=None, correlator=False, checkpoint=None, inner_tol=0.02,
+                 prec=wdt.FP16, spin=None, correlator=False, checkpoint=None, inner_tol=0.005,
                  max_batches=None):
     """Probing x time dilution x spin-colour dilution estimate of
     tr[B D^-1(t0, t0)] (B = gamma5 by default) and, with correlator=True, of
