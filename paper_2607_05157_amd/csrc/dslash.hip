@@ -133,11 +133,17 @@ static int launch_t(const wdt_gauge_s *gf, const HopSpec &hs, const void *in, vo
     h.ch = (typename S::real)hs.ch;
     h.live = hs.live;
     const int prec = prec_of<S>();
-    static const char *names[3] = {"dslash_fp64", "dslash_fp32", "dslash_fp16"};
+    // timing classes: the whole-lattice operator, one-parity pure hops, and
+    // one-parity launches with the site's own term (the even-odd operator's
+    // second half, residuals, reconstruction)
+    static const char *names[3][3] = {{"dslash_fp64", "dslash_fp32", "dslash_fp16"},
+                                      {"dslash_hop_fp64", "dslash_hop_fp32", "dslash_hop_fp16"},
+                                      {"dslash_eo_fp64", "dslash_eo_fp32", "dslash_eo_fp16"}};
+    const int kind = hs.parity < 0 ? 0 : hs.cs == 0.0 ? 1 : 2;
     // algorithmic bytes: in, out, a separate self, the epilogue's vector, links once
     const int nvec = 2 + ((hs.cs != 0.0 && hs.self && hs.self != in) ? 1 : 0) +
                      ((EPI == EPI_DOT_AUX || EPI == EPI_RESID || EPI == EPI_DOT_TSR) ? 1 : 0);
-    ProfScope prof(names[prec],
+    ProfScope prof(names[kind][prec],
                    (double)g.nsites * N * nvec * site_bytes(prec) + 4.0 * V * link_bytes(prec),
                    stream);
     switch (nc_of(N)) {

@@ -40,9 +40,6 @@ __global__ void k_scalar_omega_beta(RhsState *st, const double2 *partials, int G
 __global__ void k_scalar_check(RhsState *st, const double2 *partials, int G, int N) {
     scalar_check_body(st, partials, G, N, blockIdx.x);
 }
-__global__ void k_scalar_rho(RhsState *st, const double2 *partials, int G, int N) {
-    scalar_rho_body(st, partials, G, N, blockIdx.x);
-}
 __global__ void k_live(const RhsState *st, int N, int *live, int *host) {
     live_body(st, N, live, host);
 }
@@ -455,17 +452,6 @@ int apply_op(Bicg &B, int prec, int epi, const void *in, void *out, const void *
     return launch_hop(B.g, prec, 0, epi, h2, out, out, aux, B.N, B.part, B.sh, B.stream);
 }
 
-// r_e += (1/(2a)) H_eo r_o in place: the Schur right-hand side of the
-// correction equation; partials d0 = d1 = ||r_e||^2.
-int schur_rhs(Bicg &B, int prec, void *r) {
-    HopSpec h;
-    h.parity = 0;
-    h.self = r;
-    h.cs = 1.0;
-    h.ch = 1.0 / (2.0 * (4.0 + B.m0));
-    return launch_hop(B.g, prec, 0, EPI_NORM, h, r, r, nullptr, B.N, B.part, B.sh, B.stream);
-}
-
 // x_o = (1/a) b_o + (1/(2a)) H_oe x_e in place on the odd sites of x.
 int schur_odd(Bicg &B, int prec, const void *b, void *x) {
     const double a = 4.0 + B.m0;
@@ -583,11 +569,13 @@ static int solve_fp64(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
     const size_t st_bytes = ((sizeof(RhsState) * N + 255) / 256) * 256;
     const size_t part_off = 6 * vb;
     const size_t st_off = part_off + ((part_bytes + 255) / 256) * 256;
-    const size_t live_off = st_off + st_bytes;
+    const size_t bb_off = st_off + st_bytes;
+    const size_t live_off = bb_off + ((sizeof(double) * N + 255) / 256) * 256;
     WDT_TRY(ensure_ws(g, live_off + 256));
     char *base = (char *)g->ws.ptr;
     void *r = base, *rhat = base + vb, *p = base + 2 * vb, *v = base + 3 * vb, *s = base + 4 * vb,
          *t = base + 5 * vb;
+    double *bbv = (double *)(base + bb_off);
     Bicg B{g, m0, N, V, sh, geo, NT, dim3(sh.Gv, sh.tiles), stream,
            (RhsState *)(base + st_off), (double2 *)(base + part_off)};
     B.eo = use_even_odd(g->lat);
@@ -599,17 +587,31 @@ static int solve_fp64(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
     std::vector<int> total_it(N, 0), restarts(N, 0);
     int budget = P.max_iter;
     int rc = WDT_OK;
+    if (B.eo) {
+        // Even-odd: x_o is kept equal to (b_o + H_oe x_e / 2) / a, so the odd
+        // rows of the residual vanish, b - D x is the even-site residual of
+        // one one-parity launch, and it is also the Schur system's residual.
+        // ||b||^2 over the whole lattice, once:
+        hipLaunchKernelGGL((k_norm<F64>), B.grid, dim3(sh.threads), 0, stream, geo, N, NT, sh.SB,
+                           sp<F64>(const_cast<void *>(b), V, N), B.part);
+        hipLaunchKernelGGL(k_sum_to, dim3(N), dim3(256), 0, stream, bbv, B.part, sh.Gv, N);
+        WDT_TRY(schur_odd(B, WDT_FP64, b, x));
+    }
     for (int round = 0;; ++round) {
         // r = b - D x (true residual), rhat = r
-        WDT_TRY(launch_dslash(g, m0, WDT_FP64, 0, EPI_RESID, x, r, b, N, B.part, sh, stream));
+        if (B.eo) {
+            HopSpec h;
+            h.parity = 0;
+            h.self = x;
+            h.cs = 4.0 + m0;
+            h.ch = -0.5;
+            WDT_TRY(launch_hop(g, WDT_FP64, 0, EPI_RESID, h, x, r, b, N, B.part, sh, stream));
+        } else {
+            WDT_TRY(launch_dslash(g, m0, WDT_FP64, 0, EPI_RESID, x, r, b, N, B.part, sh, stream));
+        }
         hipLaunchKernelGGL(k_init_state, dim3(N), dim3(256), 0, stream, B.st, B.part, sh.G, N,
                            P.tol, (const int *)nullptr, (const double *)nullptr,
-                           (const double *)nullptr);
-        if (B.eo) {
-            // the correction solves M e_e = r_e + H_eo r_o / (2a); rho = its norm
-            WDT_TRY(schur_rhs(B, WDT_FP64, r));
-            hipLaunchKernelGGL(k_scalar_rho, dim3(N), dim3(256), 0, stream, B.st, B.part, sh.G, N);
-        }
+                           (const double *)(B.eo ? bbv : nullptr));
         WDT_HIP(hipMemcpyAsync(rhat, r, vb, hipMemcpyDeviceToDevice, stream));
         WDT_HIP(hipMemcpyAsync(hs.data(), B.st, sizeof(RhsState) * N, hipMemcpyDeviceToHost, stream));
         WDT_HIP(hipStreamSynchronize(stream));
