@@ -255,6 +255,26 @@ int wdt_force(wdt_gauge g, const void *dev_x, const void *dev_y, int32_t n_rhs,
 int wdt_gamma5(wdt_lattice lat, const void *dev_in, void *dev_out, int32_t n_rhs, void *stream);
 
 /*
+ * Block products for the low-mode subspace of the deflated estimator (Sec. 2,
+ * eq. defl-split: the orthogonal projector V_k V_k^dag onto k low modes of
+ * Q = Gamma5 D; the modes are found by subspace iteration with block solves
+ * and Rayleigh-Ritz, which need the same two products).  FP64 batches in the
+ * batch layout [V][12][n] (device); nx, ny in 1..64.
+ *
+ * wdt_block_dot: host_out[i*ny + j] (complex double, host, nx*ny entries) =
+ *   sum over sites and spin-colour of conj(X_i) Y_j.  Sums in a fixed order
+ *   (bit-reproducible).  Synchronises the stream.
+ * wdt_block_combine: Y_j = beta Y_j + sum_i X_i W[i*ny + j] (W host, complex
+ *   double [nx][ny]); beta = 0 overwrites Y without reading it.  dev_x and
+ *   dev_y must not overlap (WDT_EINVAL).  Synchronises the stream.
+ * Both use stream-ordered scratch of at most 1025 * nx * ny complex doubles.
+ */
+int wdt_block_dot(wdt_lattice lat, const void *dev_x, int32_t nx, const void *dev_y, int32_t ny,
+                  double *host_out, void *stream);
+int wdt_block_combine(wdt_lattice lat, const void *dev_x, int32_t nx, const double *W, int32_t ny,
+                      double beta, void *dev_y, void *stream);
+
+/*
  * Layout bridge between the natural order [n_rhs][V][12] (complex double)
  * and the batch layout [V][12][n_rhs] used above (FP64 only).
  */

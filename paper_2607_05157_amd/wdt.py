@@ -84,6 +84,8 @@ def lib():
             "wdt_force": (ctypes.c_int, [vp, vp, vp, i32, P(dbl), vp, P(dbl), vp]),
             "wdt_pack_spinor": (ctypes.c_int, [vp, vp, vp, i32, vp]),
             "wdt_gamma5": (ctypes.c_int, [vp, vp, vp, i32, vp]),
+            "wdt_block_dot": (ctypes.c_int, [vp, vp, i32, vp, i32, P(dbl), vp]),
+            "wdt_block_combine": (ctypes.c_int, [vp, vp, i32, P(dbl), i32, dbl, vp, vp]),
             "wdt_unpack_spinor": (ctypes.c_int, [vp, vp, vp, i32, vp]),
         }
         for name, (res, args) in sig.items():
@@ -274,6 +276,27 @@ def gamma5(lat, x, out, n_rhs, stream=None):
     check(lib().wdt_gamma5(lat.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                            n_rhs, _stream(stream)), "wdt_gamma5")
     return out
+
+
+def block_dot(lat, x, nx, y, ny, stream=None):
+    """[nx, ny] complex: sum over sites and spin-colour of conj(x_i) y_j (FP64
+    batches; nx, ny <= 64)."""
+    out = np.zeros((nx, ny), dtype=np.complex128)
+    check(lib().wdt_block_dot(lat.h, ctypes.c_void_p(x.data_ptr()), nx,
+                              ctypes.c_void_p(y.data_ptr()), ny,
+                              out.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              _stream(stream)), "wdt_block_dot")
+    return out
+
+
+def block_combine(lat, x, nx, W, y, ny, beta=0.0, stream=None):
+    """y_j = beta y_j + sum_i x_i W[i, j] (FP64 batches; W host [nx, ny] complex)."""
+    Wc = np.ascontiguousarray(np.asarray(W, dtype=np.complex128).reshape(nx, ny))
+    check(lib().wdt_block_combine(lat.h, ctypes.c_void_p(x.data_ptr()), nx,
+                                  Wc.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  ny, float(beta), ctypes.c_void_p(y.data_ptr()), _stream(stream)),
+          "wdt_block_combine")
+    return y
 
 
 def pack(lat, natural, batch, n_rhs, stream=None):
