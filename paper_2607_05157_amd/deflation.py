@@ -1,0 +1,123 @@
+"""Deflation of the trace estimator with low modes of Q = Gamma5 D (Sec. 2,
+eq. defl-split), on top of libwdt.
+
+Every vector operation runs in the library (block solves, the operator,
+gamma5, the block products X^dag Y and Y = beta Y + X W, contractions); this
+module only does the small dense algebra on k x k or m x m matrices
+(Cholesky, Hermitian eigenproblems) on the host.
+
+- low_modes: the k eigenpairs of Q with the smallest |lambda| by subspace
+  iteration on Q^-1 = D^-1 Gamma5 (one batched solve of the whole block per
+  step), Cholesky orthonormalisation applied twice, and Rayleigh-Ritz with Q.
+- Deflation.deflate: eta' = eta - Gamma5 V_k V_k^dag Gamma5 eta for a batch of
+  sources (two block products).
+- Deflation.exact_part: sum_i v_i^dag Gamma5 B v_i / lambda_i for the insertion
+  B = spin on slice t (one contraction).
+With these, tr(B D^-1) = exact_part + E[eta^dag B D^-1 eta'].
+"""
+import numpy as np
+
+from . import wdt
+
+GAMMA5 = np.diag([1.0, 1.0, -1.0, -1.0]).astype(np.complex128)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _apply_q(gauge, lat, m0, x, out, n):
+    """out = Gamma5 D x (FP64)."""
+    wdt.apply_D(gauge, m0, x, out, n, wdt.FP64)
+    wdt.gamma5(lat, out, out, n)
+    return out
+
+
+def _orthonormalise(lat, Z, m, tmp):
+    """Z <- Z L^-dag with Z^dag Z = L L^dag, twice (Cholesky QR 2)."""
+    for _ in range(2):
+        G = wdt.block_dot(lat, Z, m, Z, m)
+        G = 0.5 * (G + G.conj().T)
+        L = np.linalg.cholesky(G)
+        Linv_h = np.linalg.inv(L).conj().T
+        wdt.block_combine(lat, Z, m, Linv_h, tmp, m, beta=0.0)
+        Z.copy_(tmp)
+    return Z
+
+
+def low_modes(gauge, lat, m0, k, extra=16, max_iter=60, tol=1e-8, solve_tol=1e-11,
+              prec=wdt.FP16, seed=0, log=None):
+    """k eigenpairs (lambda, V_k) of Q = Gamma5 D with the smallest |lambda|.
+
+    Block of m = k + extra vectors (m <= 64): start from seeded Rademacher
+    vectors; each step solves D Z = Gamma5 X for the whole block (Z = Q^-1 X),
+    orthonormalises Z, and takes the Ritz pairs of Q on span(Z).  Stops when
+    the k wanted pairs have ||Q v - lambda v|| <= tol |lambda|.  Returns
+    (lam[k], V device batch [V][12][k], info)."""
+    torch = _torch()
+    m = k + extra
+    if not (1 <= k and m <= 64):
+        raise ValueError("need 1 <= k and k + extra <= 64")
+    X = lat.new_batch(m)
+    wdt.sources(lat, wdt.source_descs([seed * 1000 + i for i in range(m)]), X)
+    Z = lat.new_batch(m)
+    W = lat.new_batch(m)
+    tmp = lat.new_batch(m)
+    _orthonormalise(lat, X, m, tmp)
+    info = dict(iterations=0, solves=0, residuals=None)
+    lam = None
+    for it in range(1, max_iter + 1):
+        wdt.gamma5(lat, X, tmp, m)
+        Z.zero_()
+        wdt.solve(gauge, m0, tmp, Z, m, tol=solve_tol, prec=prec, max_iter=20000, max_outer=80)
+        info["solves"] += m
+        _orthonormalise(lat, Z, m, tmp)
+        _apply_q(gauge, lat, m0, Z, W, m)
+        H = wdt.block_dot(lat, Z, m, W, m)
+        H = 0.5 * (H + H.conj().T)
+        theta, S = np.linalg.eigh(H)
+        order = np.argsort(np.abs(theta), kind="stable")
+        theta, S = theta[order], S[:, order]
+        wdt.block_combine(lat, Z, m, S, X, m, beta=0.0)          # Ritz vectors
+        wdt.block_combine(lat, W, m, S, tmp, m, beta=0.0)        # Q applied to them
+        wdt.block_combine(lat, X, m, -np.diag(theta), tmp, m, beta=1.0)   # residuals
+        R = wdt.block_dot(lat, tmp, m, tmp, m)
+        res = np.sqrt(np.maximum(np.diag(R).real, 0.0))
+        lam = theta
+        info["iterations"] = it
+        info["residuals"] = res[:k] / np.abs(theta[:k])
+        if log:
+            log(f"low modes: step {it}, max relative residual {info['residuals'].max():.3e}")
+        if np.all(info["residuals"] <= tol):
+            break
+    Vk = lat.new_batch(k)
+    wdt.block_combine(lat, X, m, np.eye(m)[:, :k], Vk, k, beta=0.0)
+    del Z, W, tmp, X
+    torch.cuda.empty_cache()
+    return lam[:k], Vk, info
+
+
+class Deflation:
+    """The projector of eq. defl-split on k low modes of Q and its two uses:
+    deflating a batch of sources and the exact part of a trace."""
+
+    def __init__(self, lat, lam, Vk):
+        self.lat, self.lam, self.V = lat, np.asarray(lam), Vk
+        self.k = len(self.lam)
+        self.g5V = lat.new_batch(self.k)
+        wdt.gamma5(lat, Vk, self.g5V, self.k)
+
+    def deflate(self, b, n):
+        """b <- b - Gamma5 V_k V_k^dag Gamma5 b, in place (n <= 64 RHS)."""
+        C = wdt.block_dot(self.lat, self.g5V, self.k, b, n)      # (Gamma5 V)^dag b
+        wdt.block_combine(self.lat, self.g5V, self.k, -C, b, n, beta=1.0)
+        return b
+
+    def exact_part(self, t=None, spin=None):
+        """sum_i v_i^dag Gamma5 B v_i / lambda_i, B = spin on slice t (None: the
+        identity on the whole lattice)."""
+        S = np.eye(4) if spin is None else np.asarray(spin)
+        per = wdt.contract(self.lat, self.V, self.V, self.k, spin=GAMMA5 @ S)   # [k, Lt]
+        vals = per.sum(axis=1) if t is None else per[:, t]
+        return complex(np.sum(vals / self.lam))

@@ -11,6 +11,10 @@ which batch and adds up the per-batch pieces the library returns.
   spin-colour dilution, optionally with the slice correlator
   ||D^-1(t, t0)||_F^2; batches are checkpointed as JSON lines so an
   interrupted run resumes where it stopped.
+- probing_loop(deflation=...): the same with low modes of Q = Gamma5 D
+  deflated (Sec. 2, eq. defl-split; see deflation.py): sources deflated before
+  the solve, the contraction against the original sources, and the exact
+  low-mode part added to every seed's estimate.
 - TraceLoss: f_k = eta_k^dag D(U, m0)^-1 eta_k as a torch.autograd.Function
   whose backward is the library's link force (d f / d U, d f / d m0).
 """
@@ -62,7 +66,7 @@ def colours_on_slice(dims, n_c, sigma, t0):
 
 def probing_loop(gauge, lat, m0, n_c, sigma, t0, seeds, n_rhs=48, dilution=12, tol=1e-10,
                  prec=wdt.FP16, spin=None, correlator=False, checkpoint=None, inner_tol=0.005,
-                 max_batches=None):
+                 max_batches=None, deflation=None):
     """Probing x time dilution x spin-colour dilution estimate of
     tr[B D^-1(t0, t0)] (B = gamma5 by default) and, with correlator=True, of
     ||D^-1(t, t0)||_F^2 for every t.
@@ -71,8 +75,13 @@ def probing_loop(gauge, lat, m0, n_c, sigma, t0, seeds, n_rhs=48, dilution=12, t
     mask is off.  Each seed's estimate is the sum over its jobs; the result
     is the mean over seeds with the seed-to-seed sample variance.
     checkpoint: path of a JSON-lines file; batches already recorded there are
-    not recomputed."""
+    not recomputed.
+    deflation: a deflation.Deflation; each source eta is solved as
+    eta - Gamma5 V V^dag Gamma5 eta and contracted against eta, and the exact
+    part sum_i v_i^dag Gamma5 B v_i / lambda_i is added to every seed."""
     spin = GAMMA5 if spin is None else spin
+    if deflation is not None and correlator:
+        raise ValueError("the correlator is not deflated")
     cols = colours_on_slice(lat.dims, n_c, sigma, t0)
     comps = list(range(12)) if dilution == 12 else [None]
     jobs = [(j, s, k) for j in cols for s in seeds for k in comps]
@@ -104,8 +113,12 @@ def probing_loop(gauge, lat, m0, n_c, sigma, t0, seeds, n_rhs=48, dilution=12, t
                                  component=[x["component"] for x in descs], t0=t0)
             b = lat.new_batch(N)
             wdt.sources(lat, d, b)
+            rhs = b
+            if deflation is not None:
+                rhs = b.clone()
+                deflation.deflate(rhs, N)
             x = lat.new_batch(N)
-            _, st = wdt.solve(gauge, m0, b, x, N, tol=tol, prec=prec, inner_tol=inner_tol,
+            _, st = wdt.solve(gauge, m0, rhs, x, N, tol=tol, prec=prec, inner_tol=inner_tol,
                               max_iter=20000, max_outer=60, check_every=10)
             stats.extend(st)
             samples = wdt.contract(lat, b, x, N, spin=spin)[:, t0]
@@ -122,8 +135,12 @@ def probing_loop(gauge, lat, m0, n_c, sigma, t0, seeds, n_rhs=48, dilution=12, t
             if correlator:
                 corr[s] += norms[i]
     est = np.array([per_seed[s] for s in seeds])
+    exact = 0j
+    if deflation is not None:
+        exact = deflation.exact_part(t0, spin)
+        est = est + exact
     out = dict(per_seed=est, estimate=est.mean(), var_seeds=_var(est), colours=cols,
-               n_jobs=len(jobs), stats=stats)
+               n_jobs=len(jobs), stats=stats, exact_part=exact)
     if correlator:
         C = np.array([corr[s] for s in seeds])
         out["correlator"] = C.mean(axis=0)

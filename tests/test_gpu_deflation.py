@@ -1,0 +1,134 @@
+"""GPU checks of the deflated estimator (Sec. 2, eq. defl-split): the block
+products against numpy, the low modes of Q = Gamma5 D against a dense
+Hermitian eigensolver, and deflated probing estimates against the oracle with
+the oracle's own modes (the projector, not the basis, is what both share)."""
+import numpy as np
+import pytest
+
+from oracle import deflation as odfl, dirac, estimator as oest, gamma, noise
+from oracle import solve as osolve
+from synth.gauge import gauge_field
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+W = None
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    global W
+    from paper_2607_05157_amd import wdt
+    W = wdt
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    wdt.init(0)
+    yield
+
+
+def _rand(V, n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((V, 12, n)) + 1j * rng.standard_normal((V, 12, n))
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (7, 13), (48, 5), (64, 64)])
+def test_block_dot_and_combine_match_numpy(nx, ny):
+    dims = (4, 4, 2, 6)
+    say("block products", nx, ny)
+    V = int(np.prod(dims))
+    lat = W.Lattice(dims, -1)
+    X, Y = _rand(V, nx, 1), _rand(V, ny, 2)
+    Xm, Ym = X.reshape(-1, nx), Y.reshape(-1, ny)
+    G = W.block_dot(lat, _dev(X), nx, _dev(Y), ny)
+    ref = Xm.conj().T @ Ym
+    assert np.max(np.abs(G - ref)) < 1e-12 * np.max(np.abs(ref))
+    Wm = np.random.default_rng(3).standard_normal((nx, ny)) + 0j
+    for beta in (0.0, 1.0, -0.5):
+        y = _dev(Y)
+        W.block_combine(lat, _dev(X), nx, Wm, y, ny, beta=beta)
+        want = beta * Ym + Xm @ Wm
+        got = y.cpu().numpy().reshape(-1, ny)
+        assert np.max(np.abs(got - want)) < 1e-12 * np.max(np.abs(want)), beta
+
+
+def test_block_combine_rejects_overlap():
+    lat = W.Lattice((4, 4, 2, 6), -1)
+    x = lat.new_batch(4)
+    with pytest.raises(RuntimeError):
+        W.block_combine(lat, x, 4, np.eye(4), x, 4)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    # a negative bare mass brings low modes of Q down (smallest |lambda| 0.42
+    # against 0.93 at m0 = 0.05 on this field)
+    dims, m0 = (4, 4, 2, 4), -0.6
+    U = gauge_field(dims, 0.5, seed=31)
+    D = dirac.dense_D(U, m0, dims, -1)
+    lam_all, vec_all = odfl.low_modes(odfl.q_matrix(D), D.shape[0])
+    # k where the spectrum has a gap, so the subspace is well defined
+    a = np.abs(lam_all)
+    k = next(k for k in range(6, 15) if a[k] > 1.03 * a[k - 1])
+    return dims, m0, U, D, osolve.dense_inverse(D), k, lam_all
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_low_modes_match_dense_eigensolver(c2, prec):
+    from paper_2607_05157_amd import deflation
+    dims, m0, U, D, Dinv, k, lam_all = c2
+    say("low modes", dims, "k", k, prec)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    p = W.FP64 if prec == "fp64" else W.FP16
+    lam, Vk, info = deflation.low_modes(g, lat, m0, k, extra=16, tol=1e-9, prec=p,
+                                        solve_tol=1e-12 if p == W.FP64 else 1e-11)
+    assert np.all(info["residuals"] <= 1e-9), info
+    ref_lam, ref_V = odfl.low_modes(odfl.q_matrix(D), k)
+    assert np.max(np.abs(lam - ref_lam) / np.abs(ref_lam)) < 1e-9
+    Vg = Vk.cpu().numpy().reshape(-1, k)
+    # orthonormal, and the same projector as the dense modes
+    assert np.max(np.abs(Vg.conj().T @ Vg - np.eye(k))) < 1e-12
+    P_g, P_o = Vg @ Vg.conj().T, ref_V @ ref_V.conj().T
+    assert np.linalg.norm(P_g - P_o, 2) < 1e-6
+
+
+def test_deflated_probing_matches_oracle(c2):
+    """Spin-colour diluted, time-diluted Hutchinson on slice t0 with k modes
+    deflated: per-seed estimates (exact part + deflated samples) against the
+    oracle's, and the exact part alone."""
+    from paper_2607_05157_amd import deflation, estimator
+    dims, m0, U, D, Dinv, k, _ = c2
+    t0, seeds = 1, [0, 1, 2]
+    say("deflated probing", dims, k)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    lam, Vk, info = deflation.low_modes(g, lat, m0, k, extra=16, tol=1e-10, prec=W.FP64,
+                                        solve_tol=1e-12)
+    dfl = deflation.Deflation(lat, lam, Vk)
+    out = estimator.probing_loop(g, lat, m0, 1, (0, 0, 0, 0), t0, seeds, n_rhs=36, tol=1e-12,
+                                 prec=W.FP64, deflation=dfl)
+    ref_lam, ref_V = odfl.low_modes(odfl.q_matrix(D), k)
+    ex = odfl.exact_part(ref_lam, ref_V, dims, t0, gamma.GAMMA5)
+    assert abs(out["exact_part"] - ex) < 1e-8 * max(1.0, abs(ex))
+    V = int(np.prod(dims))
+    col = np.zeros(V, dtype=int)
+    ref = []
+    for s in seeds:
+        tot = 0j
+        for c in range(12):
+            v = noise.probing_vector(dims, s, col, 0, c, t0).ravel()
+            tot += odfl.deflated_sample(Dinv, ref_V, v, dims, t0, gamma.GAMMA5)
+        ref.append(tot + ex)
+    ref = np.array(ref)
+    assert np.max(np.abs(out["per_seed"] - ref)) < 1e-8 * max(1.0, np.max(np.abs(ref)))
+    # the deflated estimate agrees with the exact loop within its error
+    exact = oest.exact_loop(Dinv, dims, t0)
+    assert abs(out["estimate"] - exact) < 6 * np.sqrt(out["var_seeds"] / len(seeds)) + 1e-8
