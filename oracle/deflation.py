@@ -8,15 +8,20 @@ Pi = V_k V_k^dag is the orthogonal projector of eq. defl-split.  Since
 D^-1 = Q^-1 Gamma5 and Q^-1 Pi = sum_i v_i v_i^dag / lambda_i, for any
 insertion B (a spin matrix on one time slice, or the identity):
 
-  tr(B D^-1) = sum_i v_i^dag Gamma5 B v_i / lambda_i             exact part
+  tr(B D^-1) = tr(B D^-1 Gamma5 Pi Gamma5)                      low-mode part
              + tr(B D^-1 (I - Gamma5 Pi Gamma5))                  stochastic part
 
-(B D^-1 Gamma5 Pi Gamma5 = B Q^-1 Pi Gamma5, whose trace is the sum above).
+for ANY V_k with orthonormal columns; the low-mode part is computed exactly
+with k solves, sum_i (Gamma5 v_i)^dag B D^-1 (Gamma5 v_i) (the paper's "exact
+computation involving k linear solves").  For exact eigenvectors it reduces
+to sum_i v_i^dag Gamma5 B v_i / lambda_i, since then B D^-1 Gamma5 Pi Gamma5 =
+B Q^-1 Pi Gamma5.
 The stochastic part is sampled with deflated sources
 eta' = eta - Gamma5 V_k V_k^dag Gamma5 eta, one sample being
-eta^dag B D^-1 eta'.  With B = 1 the exact part is tr(Pi D^-1) of the paper's
-split; the projector acts on the source side (as Gamma5 Pi Gamma5) so that the
-exact part stays a closed form for every B and the contraction is unchanged.
+eta^dag B D^-1 eta'.  With B = 1 and eigenvectors the low-mode part is
+tr(Pi D^-1) of the paper's split; the projector acts on the source side (as
+Gamma5 Pi Gamma5) so that the contraction is unchanged and the eigenvector
+closed form holds for every B.
 D^-1 (I - Gamma5 Pi Gamma5) = Q^-1 (I - Pi) Gamma5 has spectral norm
 1 / |lambda_{k+1}|: the low modes that dominate the variance (Sec. 2, first
 paragraph) are gone from the sampled part.
@@ -54,6 +59,17 @@ def exact_part(lam, Vk, dims, t=None, spin=None):
     for i in range(len(lam)):
         v = Vk[:, i].reshape(-1, 12)
         tot += sample_dot(v, v, dims, t, GAMMA5 @ S) / lam[i]
+    return tot
+
+
+def exact_part_solves(Dinv, Vk, dims, t=None, spin=None):
+    """sum_i (Gamma5 v_i)^dag B D^-1 (Gamma5 v_i), B = spin on slice t: the
+    low-mode part for any orthonormal V_k."""
+    g5 = gamma5_full(Vk.shape[0] // 12)
+    tot = 0j
+    for i in range(Vk.shape[1]):
+        w = g5 * Vk[:, i]
+        tot += sample_dot(w.reshape(-1, 12), (Dinv @ w).reshape(-1, 12), dims, t, spin)
     return tot
 
 

@@ -11,8 +11,12 @@ module only does the small dense algebra on k x k or m x m matrices
   step), Cholesky orthonormalisation applied twice, and Rayleigh-Ritz with Q.
 - Deflation.deflate: eta' = eta - Gamma5 V_k V_k^dag Gamma5 eta for a batch of
   sources (two block products).
-- Deflation.exact_part: sum_i v_i^dag Gamma5 B v_i / lambda_i for the insertion
-  B = spin on slice t (one contraction).
+- Deflation.exact_part: the low-mode part tr(B D^-1 Gamma5 Pi Gamma5) =
+  sum_i (Gamma5 v_i)^dag B D^-1 Gamma5 v_i for the insertion B = spin on
+  slice t, by one batched solve of the k vectors Gamma5 v_i (exact for any
+  orthonormal V_k, so modes that are not fully converged cost variance
+  reduction, not bias); exact_part_eig is the closed form
+  sum_i v_i^dag Gamma5 B v_i / lambda_i, equal to it for exact eigenvectors.
 With these, tr(B D^-1) = exact_part + E[eta^dag B D^-1 eta'].
 """
 import numpy as np
@@ -114,9 +118,18 @@ class Deflation:
         wdt.block_combine(self.lat, self.g5V, self.k, -C, b, n, beta=1.0)
         return b
 
-    def exact_part(self, t=None, spin=None):
-        """sum_i v_i^dag Gamma5 B v_i / lambda_i, B = spin on slice t (None: the
-        identity on the whole lattice)."""
+    def exact_part(self, gauge, m0, t=None, spin=None, tol=1e-10, prec=wdt.FP16):
+        """sum_i (Gamma5 v_i)^dag B D^-1 (Gamma5 v_i), B = spin on slice t (None:
+        the whole lattice; spin None: the identity), by one batched solve."""
+        y = self.lat.new_batch(self.k)
+        wdt.solve(gauge, m0, self.g5V, y, self.k, tol=tol, prec=prec, max_iter=20000,
+                  max_outer=80)
+        per = wdt.contract(self.lat, self.g5V, y, self.k, spin=spin)   # [k, Lt]
+        vals = per.sum(axis=1) if t is None else per[:, t]
+        return complex(np.sum(vals))
+
+    def exact_part_eig(self, t=None, spin=None):
+        """sum_i v_i^dag Gamma5 B v_i / lambda_i (exact eigenvectors only)."""
         S = np.eye(4) if spin is None else np.asarray(spin)
         per = wdt.contract(self.lat, self.V, self.V, self.k, spin=GAMMA5 @ S)   # [k, Lt]
         vals = per.sum(axis=1) if t is None else per[:, t]

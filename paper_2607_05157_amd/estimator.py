@@ -77,8 +77,9 @@ def probing_loop(gauge, lat, m0, n_c, sigma, t0, seeds, n_rhs=48, dilution=12, t
     checkpoint: path of a JSON-lines file; batches already recorded there are
     not recomputed.
     deflation: a deflation.Deflation; each source eta is solved as
-    eta - Gamma5 V V^dag Gamma5 eta and contracted against eta, and the exact
-    part sum_i v_i^dag Gamma5 B v_i / lambda_i is added to every seed."""
+    eta - Gamma5 V V^dag Gamma5 eta and contracted against eta, and the
+    low-mode part tr(B D^-1 Gamma5 V V^dag Gamma5) (k solves) is added to
+    every seed."""
     spin = GAMMA5 if spin is None else spin
     if deflation is not None and correlator:
         raise ValueError("the correlator is not deflated")
@@ -137,7 +138,7 @@ def probing_loop(gauge, lat, m0, n_c, sigma, t0, seeds, n_rhs=48, dilution=12, t
     est = np.array([per_seed[s] for s in seeds])
     exact = 0j
     if deflation is not None:
-        exact = deflation.exact_part(t0, spin)
+        exact = deflation.exact_part(gauge, m0, t0, spin, tol=tol, prec=prec)
         est = est + exact
     out = dict(per_seed=est, estimate=est.mean(), var_seeds=_var(est), colours=cols,
                n_jobs=len(jobs), stats=stats, exact_part=exact)

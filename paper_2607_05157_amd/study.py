@@ -10,7 +10,10 @@ Each row is one estimator:
   dil12       eta restricted to t0, one solve per spin-colour component;
   probe dD    colours of a distance-D torus colouring (of the time slice,
               dim=3, or of the whole lattice, dim=4) present on t0, times
-              spin-colour dilution: (colours on t0) x 12 solves per sample.
+              spin-colour dilution: (colours on t0) x 12 solves per sample;
+  ... +defl k the same with the k lowest modes of Q = Gamma5 D deflated
+              (Sec. 2, eq. defl-split): the exact low-mode part plus deflated
+              samples; the modes cost a one-off setup (setup_solves).
 For each: the mean over seeds, the seed-to-seed sample variance (complex,
 N - 1), the solves one sample costs, their product (solves per unit of
 inverse variance: the figure of merit) and N_total = solves per sample x
@@ -48,19 +51,47 @@ def colouring(dims, d, dim):
 
 
 def run(gauge, lat, m0, t0, seeds, distances=(1, 2, 3, 4), dim=3, eps=None, n_rhs=48,
-        prec=wdt.FP16, tol=1e-10, baselines=True, log=None):
+        prec=wdt.FP16, tol=1e-10, baselines=True, log=None, deflate=(), defl_distances=None):
+    """Rows of the study.  deflate: numbers of low modes k; each k repeats the
+    baselines (and the colourings in defl_distances) with k modes deflated."""
     rows = []
     specs = []
     if baselines:
-        specs.append(("hutchinson", 0, 1, (0, 0, 0, 0), 1))
-        specs.append(("dil12", 0, 1, (0, 0, 0, 0), 12))
+        specs.append(("hutchinson", 0, 1, (0, 0, 0, 0), 1, 0))
+        specs.append(("dil12", 0, 1, (0, 0, 0, 0), 12, 0))
     for d in distances:
         n_c, sigma = colouring(lat.dims, d, dim)
-        specs.append((f"probe d{d}", d, n_c, sigma, 12))
-    for name, d, n_c, sigma, dil in specs:
+        specs.append((f"probe d{d}", d, n_c, sigma, 12, 0))
+    setup = {}
+    if deflate:
+        from . import deflation
+        kmax = max(deflate)
+        t = time.perf_counter()
+        lam, Vk, info = deflation.low_modes(gauge, lat, m0, kmax, extra=min(16, 64 - kmax),
+                                            tol=1e-8, prec=prec, log=log)
+        setup = dict(seconds=round(time.perf_counter() - t, 3), solves=info["solves"],
+                     iterations=info["iterations"], lam_abs_min=float(abs(lam).min()),
+                     lam_abs_max=float(abs(lam).max()))
+        if log:
+            log(json.dumps(dict(low_modes=kmax, **setup)))
+        for k in sorted(deflate):
+            for d in ([0] + list(defl_distances or [])):
+                if d == 0:
+                    for name, dil in (("hutchinson", 1), ("dil12", 12)):
+                        specs.append((f"{name}+defl{k}", 0, 1, (0, 0, 0, 0), dil, k))
+                else:
+                    n_c, sigma = colouring(lat.dims, d, dim)
+                    specs.append((f"probe d{d}+defl{k}", d, n_c, sigma, 12, k))
+    defl_cache = {}
+    for name, d, n_c, sigma, dil, k in specs:
+        dfl = None
+        if k:
+            if k not in defl_cache:
+                defl_cache[k] = deflation.Deflation(lat, lam[:k], Vk[:, :, :k].contiguous())
+            dfl = defl_cache[k]
         t = time.perf_counter()
         out = estimator.probing_loop(gauge, lat, m0, n_c, sigma, t0, list(seeds), n_rhs=n_rhs,
-                                     dilution=dil, tol=tol, prec=prec)
+                                     dilution=dil, tol=tol, prec=prec, deflation=dfl)
         dt = time.perf_counter() - t
         solves = len(out["colours"]) * (12 if dil == 12 else 1)
         var = out["var_seeds"]
@@ -68,14 +99,17 @@ def run(gauge, lat, m0, t0, seeds, distances=(1, 2, 3, 4), dim=3, eps=None, n_rh
                    colours_on_slice=len(out["colours"]), solves_per_sample=solves,
                    estimate=[out["estimate"].real, out["estimate"].imag], variance=var,
                    std_error=math.sqrt(var / len(seeds)), seeds=len(seeds), seconds=round(dt, 3),
-                   cost=solves * var,
+                   cost=solves * var, deflated_modes=k,
+                   setup_solves=setup.get("solves", 0) if k else 0,
                    per_seed_re=out["per_seed"].real.tolist(),
                    per_seed_im=out["per_seed"].imag.tolist())
+        if k:
+            row["exact_part"] = [out["exact_part"].real, out["exact_part"].imag]
         if eps:
-            row["n_total"] = solves * max(1, math.ceil(var / eps ** 2))
+            row["n_total"] = solves * max(1, math.ceil(var / eps ** 2)) + row["setup_solves"]
         rows.append(row)
         if log:
-            log(json.dumps({k: v for k, v in row.items() if not k.startswith("per_seed")}))
+            log(json.dumps({k_: v for k_, v in row.items() if not k_.startswith("per_seed")}))
     return rows
 
 
@@ -90,6 +124,10 @@ def main(argv=None):
     ap.add_argument("--distances", type=int, nargs="+", default=[1, 2, 3, 4])
     ap.add_argument("--dim", type=int, default=3, choices=[3, 4])
     ap.add_argument("--eps", type=float, default=None, help="target standard error for N_total")
+    ap.add_argument("--deflate", type=int, nargs="*", default=[],
+                    help="numbers of low modes of Gamma5 D to deflate (each <= 48)")
+    ap.add_argument("--defl-distances", type=int, nargs="*", default=[],
+                    help="colouring distances also run with deflation")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     from synth.gauge import gauge_field
@@ -98,7 +136,8 @@ def main(argv=None):
     lat = wdt.Lattice(dims, -1)
     g = wdt.Gauge(lat, gauge_field(dims, a.eps_link, a.gauge_seed))
     rows = run(g, lat, a.m0, a.t0, range(a.seeds), a.distances, a.dim, a.eps,
-               log=lambda s: print(s, flush=True))
+               log=lambda s: print(s, flush=True), deflate=a.deflate,
+               defl_distances=a.defl_distances)
     if a.out:
         json.dump(dict(dims=list(dims), m0=a.m0, eps_link=a.eps_link, rows=rows), open(a.out, "w"),
                   indent=1)

@@ -44,6 +44,27 @@ def test_split_reproduces_dense_trace(small, k, where):
     assert abs(tot - ref) < 1e-11 * max(1.0, abs(ref))
 
 
+@pytest.mark.parametrize("where", ["lattice", "slice"])
+def test_split_holds_for_any_orthonormal_basis(small, where):
+    """With the low-mode part taken by solves, the split is exact for any
+    orthonormal V_k (here random), and for eigenvectors the solve form
+    equals the eigenvalue form."""
+    dims, D, Dinv = small
+    n = D.shape[0]
+    rng = np.random.default_rng(5)
+    Vr, _ = np.linalg.qr(rng.standard_normal((n, 7)) + 1j * rng.standard_normal((n, 7)))
+    if where == "lattice":
+        t, spin, ref = None, None, np.trace(Dinv)
+    else:
+        t, spin, ref = 3, GAMMA5, estimator.exact_loop(Dinv, dims, 3)
+    tot = dfl.exact_part_solves(Dinv, Vr, dims, t, spin) + dfl.stochastic_trace(Dinv, Vr, dims, t, spin)
+    assert abs(tot - ref) < 1e-11 * max(1.0, abs(ref))
+    lam, Vk = dfl.low_modes(dfl.q_matrix(D), 9)
+    a = dfl.exact_part_solves(Dinv, Vk, dims, t, spin)
+    b = dfl.exact_part(lam, Vk, dims, t, spin)
+    assert abs(a - b) < 1e-11 * max(1.0, abs(b))
+
+
 def test_full_deflation_leaves_nothing_to_sample(small):
     dims, D, Dinv = small
     n = D.shape[0]
