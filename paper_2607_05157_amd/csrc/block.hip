@@ -16,52 +16,103 @@ namespace wdt {
 constexpr int kBlockMax = 64;  // largest nx, ny
 constexpr int kDotSites = 2;   // sites staged in LDS per step
 
+// Threads of k_block_dot: ceil(nx/4) x ceil(ny/4) tiles of 4 x 4 entries,
+// and as many groups of them as fit in 256 threads; group g takes every
+// groups-th staged row and writes its own partial.
+__host__ __device__ inline int dot_groups(int nx, int ny) {
+    const int ntile = ((nx + 3) / 4) * ((ny + 3) / 4);
+    return ntile >= 256 ? 1 : 256 / ntile;
+}
+// sites staged per step: as many as the LDS arrays hold for these widths
+__host__ __device__ inline int dot_sites(int nx, int ny) {
+    const int w = nx > ny ? nx : ny;
+    const int s = kDotSites * kBlockMax / w;
+    return s < 1 ? 1 : s > 16 ? 16 : s;
+}
+
 // Per-block partial sums of X^dag Y: block b accumulates its share of the
-// sites; thread t owns the entries e = t + 256 m (i = e / ny, j = e % ny).
+// sites, staged dot_sites at a time in LDS.  A thread owns a 4 x 4 tile of
+// entries: per staged row it reads 4 X and 4 Y elements for 16 complex
+// multiply-adds.  The groups' tiles are added up in LDS in group order;
+// partials: [G][nx * ny].
 __global__ __launch_bounds__(256) void k_block_dot(const double2 *__restrict__ X, int nx,
                                                    const double2 *__restrict__ Y, int ny,
                                                    int64_t V, double2 *__restrict__ part) {
-    __shared__ double2 xs[kDotSites * 12 * kBlockMax];
-    __shared__ double2 ys[kDotSites * 12 * kBlockMax];
+    __shared__ double2 stage[2 * kDotSites * 12 * kBlockMax];
+    double2 *xs = stage, *ys = stage + kDotSites * 12 * kBlockMax;
     const int tid = threadIdx.x;
-    const int ne = nx * ny;
-    constexpr int M = kBlockMax * kBlockMax / 256;
-    double ar[M], ai[M];
+    const int ty = (ny + 3) / 4, ntile = ((nx + 3) / 4) * ty;
+    const int groups = dot_groups(nx, ny), spb = dot_sites(nx, ny);
+    const int g = tid / ntile, tile = tid - (tid / ntile) * ntile;
+    const bool act = g < groups;
+    const int i0 = 4 * (tile / ty), j0 = 4 * (tile % ty);
+    double ar[4][4], ai[4][4];
 #pragma unroll
-    for (int m = 0; m < M; ++m) ar[m] = ai[m] = 0.0;
-    const int64_t nsteps = (V + kDotSites - 1) / kDotSites;
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ar[a][c] = ai[a][c] = 0.0;
+    const int64_t nsteps = (V + spb - 1) / spb;
     for (int64_t st = blockIdx.x; st < nsteps; st += gridDim.x) {
-        const int64_t s0 = st * kDotSites;
-        const int ns = (int)((V - s0) < kDotSites ? (V - s0) : kDotSites);
+        const int64_t s0 = st * spb;
+        const int ns = (int)((V - s0) < spb ? (V - s0) : spb);
         const int nxr = ns * 12 * nx, nyr = ns * 12 * ny;
         __syncthreads();
         for (int q = tid; q < nxr; q += 256) xs[q] = X[s0 * 12 * nx + q];
         for (int q = tid; q < nyr; q += 256) ys[q] = Y[s0 * 12 * ny + q];
         __syncthreads();
+        if (act) {
+            for (int rrow = g; rrow < ns * 12; rrow += groups) {
+                double2 xa[4], yc[4];
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const int e = tid + 256 * m;
-            if (e >= ne) break;
-            const int i = e / ny, j = e - (e / ny) * ny;
-            double sr = 0.0, si = 0.0;
-            for (int rrow = 0; rrow < ns * 12; ++rrow) {
-                const double2 a = xs[rrow * nx + i], b = ys[rrow * ny + j];
-                // conj(a) b
-                sr += a.x * b.x + a.y * b.y;
-                si += a.x * b.y - a.y * b.x;
+                for (int a = 0; a < 4; ++a)
+                    xa[a] = (i0 + a < nx) ? xs[rrow * nx + i0 + a] : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    yc[c] = (j0 + c < ny) ? ys[rrow * ny + j0 + c] : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        // conj(x) y
+                        ar[a][c] += xa[a].x * yc[c].x + xa[a].y * yc[c].y;
+                        ai[a][c] += xa[a].x * yc[c].y - xa[a].y * yc[c].x;
+                    }
             }
-            ar[m] += sr;
-            ai[m] += si;
         }
     }
+    const int ne = nx * ny;
+    double2 *pp = part + (size_t)blockIdx.x * ne;
+    if (groups == 1) {
+        if (!act) return;
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        const int e = tid + 256 * m;
-        if (e < ne) part[(size_t)blockIdx.x * ne + e] = make_double2(ar[m], ai[m]);
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (i0 + a < nx && j0 + c < ny)
+                    pp[(i0 + a) * ny + j0 + c] = make_double2(ar[a][c], ai[a][c]);
+        return;
     }
+    // groups > 1 means ntile <= 128, so ne <= 2048 fits the staging area
+    double2 *acc = stage;
+    __syncthreads();
+    for (int gg = 0; gg < groups; ++gg) {
+        if (g == gg) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (i0 + a < nx && j0 + c < ny) {
+                        const int e = (i0 + a) * ny + j0 + c;
+                        const double2 o = gg ? acc[e] : make_double2(0.0, 0.0);
+                        acc[e] = make_double2(o.x + ar[a][c], o.y + ai[a][c]);
+                    }
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < ne; e += 256) pp[e] = acc[e];
 }
 
-// out[e] = sum over the G block partials, in block order.
+// out[e] = sum over the G partials, in order.
 __global__ void k_block_dot_reduce(const double2 *__restrict__ part, int G, int ne,
                                    double2 *__restrict__ out) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -76,31 +127,63 @@ __global__ void k_block_dot_reduce(const double2 *__restrict__ part, int G, int 
 }
 
 // Y[row][j] = beta Y[row][j] + sum_i X[row][i] W[i][j], rows = 12 V (site,
-// spin-colour); one thread per output element, j fastest (coalesced stores;
-// the X row is read by the ny threads of one row together).
+// spin-colour).  W is staged in LDS once per block; each thread computes a
+// tile of kRows consecutive rows x kCols consecutive columns, so per i it
+// reads kRows X elements and kCols W elements for kRows x kCols complex
+// multiply-adds (column groups fastest across threads: coalesced stores).
+constexpr int kCols = 4, kRows = 4;
 __global__ __launch_bounds__(256) void k_block_combine(const double2 *__restrict__ X, int nx,
                                                        const double2 *__restrict__ W, int ny,
                                                        double beta, int64_t rows,
                                                        double2 *__restrict__ Y) {
-    const int64_t n = rows * ny;
+    __shared__ double2 ws[kBlockMax * kBlockMax];
+    for (int q = threadIdx.x; q < nx * ny; q += blockDim.x) ws[q] = W[q];
+    __syncthreads();
+    const int ngr = (ny + kCols - 1) / kCols;        // column groups per row group
+    const int64_t nrg = (rows + kRows - 1) / kRows;  // row groups
+    const int64_t n = nrg * ngr;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t row = q / ny;
-        const int j = (int)(q - row * ny);
-        const double2 *xr = X + row * nx;
-        double sr = 0.0, si = 0.0;
+        const int64_t r0 = (q / ngr) * kRows;
+        const int j0 = (int)(q % ngr) * kCols;
+        double sr[kRows][kCols], si[kRows][kCols];
+#pragma unroll
+        for (int a = 0; a < kRows; ++a)
+#pragma unroll
+            for (int c = 0; c < kCols; ++c) sr[a][c] = si[a][c] = 0.0;
         for (int i = 0; i < nx; ++i) {
-            const double2 a = xr[i], w = W[i * ny + j];
-            sr += a.x * w.x - a.y * w.y;
-            si += a.x * w.y + a.y * w.x;
+            double2 xa[kRows], wc[kCols];
+#pragma unroll
+            for (int a = 0; a < kRows; ++a)
+                xa[a] = (r0 + a < rows) ? X[(r0 + a) * nx + i] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int c = 0; c < kCols; ++c)
+                wc[c] = (j0 + c < ny) ? ws[i * ny + j0 + c] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int a = 0; a < kRows; ++a)
+#pragma unroll
+                for (int c = 0; c < kCols; ++c) {
+                    sr[a][c] += xa[a].x * wc[c].x - xa[a].y * wc[c].y;
+                    si[a][c] += xa[a].x * wc[c].y + xa[a].y * wc[c].x;
+                }
         }
-        double2 y = make_double2(sr, si);
-        if (beta != 0.0) {
-            const double2 o = Y[q];
-            y.x += beta * o.x;
-            y.y += beta * o.y;
+#pragma unroll
+        for (int a = 0; a < kRows; ++a) {
+            if (r0 + a >= rows) break;
+            double2 *yr = Y + (r0 + a) * ny + j0;
+#pragma unroll
+            for (int c = 0; c < kCols; ++c) {
+                if (j0 + c < ny) {
+                    double2 y = make_double2(sr[a][c], si[a][c]);
+                    if (beta != 0.0) {
+                        const double2 o = yr[c];
+                        y.x += beta * o.x;
+                        y.y += beta * o.y;
+                    }
+                    yr[c] = y;
+                }
+            }
         }
-        Y[q] = y;
     }
 }
 
@@ -117,16 +200,17 @@ int wdt_block_dot(wdt_lattice lat, const void *dev_x, int32_t nx, const void *de
               "wdt_block_dot: nx and ny must be 1..%d", kBlockMax);
     const hipStream_t st = (hipStream_t)stream;
     const int ne = nx * ny;
-    const int64_t nsteps = (lat->V + kDotSites - 1) / kDotSites;
+    const int64_t nsteps = (lat->V + dot_sites(nx, ny) - 1) / dot_sites(nx, ny);
     const int G = (int)std::min<int64_t>(nsteps, 1024);
+    const int np = G;  // partials
     AsyncScratch scratch(st);
-    if (!scratch.alloc(sizeof(double2) * ((size_t)G + 1) * ne))
+    if (!scratch.alloc(sizeof(double2) * ((size_t)np + 1) * ne))
         return set_error(WDT_ENOMEM, "wdt_block_dot: scratch allocation failed");
     double2 *part = (double2 *)scratch.p;
-    double2 *out = part + (size_t)G * ne;
+    double2 *out = part + (size_t)np * ne;
     hipLaunchKernelGGL(k_block_dot, dim3(G), dim3(256), 0, st, (const double2 *)dev_x, nx,
                        (const double2 *)dev_y, ny, lat->V, part);
-    hipLaunchKernelGGL(k_block_dot_reduce, dim3((ne + 255) / 256), dim3(256), 0, st, part, G, ne,
+    hipLaunchKernelGGL(k_block_dot_reduce, dim3((ne + 255) / 256), dim3(256), 0, st, part, np, ne,
                        out);
     WDT_HIP(hipGetLastError());
     WDT_HIP(hipMemcpyAsync(host_out, out, sizeof(double2) * ne, hipMemcpyDeviceToHost, st));
@@ -152,8 +236,10 @@ int wdt_block_combine(wdt_lattice lat, const void *dev_x, int32_t nx, const doub
         return set_error(WDT_ENOMEM, "wdt_block_combine: scratch allocation failed");
     double2 *dw = (double2 *)scratch.p;
     WDT_HIP(hipMemcpyAsync(dw, W, sizeof(double2) * (size_t)nx * ny, hipMemcpyHostToDevice, st));
-    const int64_t n = rows * ny;
-    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    // about the blocks the GPU holds at once (64 KB of LDS each): every block
+    // stages W once and then strides over the rows
+    const int64_t n = ((rows + kRows - 1) / kRows) * ((ny + kCols - 1) / kCols);
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 512);
     hipLaunchKernelGGL(k_block_combine, dim3(blocks), dim3(256), 0, st, (const double2 *)dev_x, nx,
                        dw, ny, beta, rows, (double2 *)dev_y);
     WDT_HIP(hipGetLastError());

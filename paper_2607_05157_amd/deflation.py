@@ -8,7 +8,10 @@ module only does the small dense algebra on k x k or m x m matrices
 
 - low_modes: the k eigenpairs of Q with the smallest |lambda| by subspace
   iteration on Q^-1 = D^-1 Gamma5 (one batched solve of the whole block per
-  step), Cholesky orthonormalisation applied twice, and Rayleigh-Ritz with Q.
+  step), Cholesky orthonormalisation applied twice, and Rayleigh-Ritz: first
+  with Q^2 = (Q Z)^dag (Q Z) to pick the k-dimensional subspace of smallest
+  |lambda| (Q is indefinite, so Ritz values of Q alone can be spurious near
+  zero, mixtures of +lambda and -lambda modes), then with Q inside it.
 - Deflation.deflate: eta' = eta - Gamma5 V_k V_k^dag Gamma5 eta for a batch of
   sources (two block products).
 - Deflation.exact_part: the low-mode part tr(B D^-1 Gamma5 Pi Gamma5) =
@@ -78,19 +81,25 @@ def low_modes(gauge, lat, m0, k, extra=16, max_iter=60, tol=1e-8, solve_tol=1e-1
         info["solves"] += m
         _orthonormalise(lat, Z, m, tmp)
         _apply_q(gauge, lat, m0, Z, W, m)
-        H = wdt.block_dot(lat, Z, m, W, m)
+        H = wdt.block_dot(lat, Z, m, W, m)           # Z^dag Q Z
         H = 0.5 * (H + H.conj().T)
-        theta, S = np.linalg.eigh(H)
+        H2 = wdt.block_dot(lat, W, m, W, m)          # Z^dag Q^2 Z
+        H2 = 0.5 * (H2 + H2.conj().T)
+        _, S2 = np.linalg.eigh(H2)                   # ascending: smallest |lambda| first
+        Sk = S2[:, :k]
+        theta, T = np.linalg.eigh(Sk.conj().T @ H @ Sk)
         order = np.argsort(np.abs(theta), kind="stable")
-        theta, S = theta[order], S[:, order]
-        wdt.block_combine(lat, Z, m, S, X, m, beta=0.0)          # Ritz vectors
-        wdt.block_combine(lat, W, m, S, tmp, m, beta=0.0)        # Q applied to them
-        wdt.block_combine(lat, X, m, -np.diag(theta), tmp, m, beta=1.0)   # residuals
-        R = wdt.block_dot(lat, tmp, m, tmp, m)
-        res = np.sqrt(np.maximum(np.diag(R).real, 0.0))
+        theta, T = theta[order], T[:, order]
+        C = np.concatenate([Sk @ T, S2[:, k:]], axis=1)   # unitary m x m
+        wdt.block_combine(lat, Z, m, C, X, m, beta=0.0)          # new block, wanted first
+        wdt.block_combine(lat, W, m, C, tmp, m, beta=0.0)        # Q applied to it
+        dth = np.zeros((m, m), dtype=complex)
+        dth[np.arange(k), np.arange(k)] = -theta
+        wdt.block_combine(lat, X, m, dth, tmp, m, beta=1.0)      # residuals of the k wanted
+        res = np.sqrt(wdt.contract(lat, None, tmp, m, mode=wdt.CONTRACT_NORM2).sum(axis=1))
         lam = theta
         info["iterations"] = it
-        info["residuals"] = res[:k] / np.abs(theta[:k])
+        info["residuals"] = res[:k] / np.abs(theta)
         if log:
             log(f"low modes: step {it}, max relative residual {info['residuals'].max():.3e}")
         if np.all(info["residuals"] <= tol):
@@ -99,7 +108,7 @@ def low_modes(gauge, lat, m0, k, extra=16, max_iter=60, tol=1e-8, solve_tol=1e-1
     wdt.block_combine(lat, X, m, np.eye(m)[:, :k], Vk, k, beta=0.0)
     del Z, W, tmp, X
     torch.cuda.empty_cache()
-    return lam[:k], Vk, info
+    return lam, Vk, info
 
 
 class Deflation:

@@ -64,7 +64,7 @@ def run(gauge, lat, m0, t0, seeds, distances=(1, 2, 3, 4), dim=3, eps=None, n_rh
         specs.append((f"probe d{d}", d, n_c, sigma, 12, 0))
     setup = {}
     if deflate:
-        from . import deflation
+        from paper_2607_05157_amd import deflation
         kmax = max(deflate)
         t = time.perf_counter()
         lam, Vk, info = deflation.low_modes(gauge, lat, m0, kmax, extra=min(16, 64 - kmax),
@@ -121,13 +121,15 @@ def main(argv=None):
     ap.add_argument("--m0", type=float, default=0.02)
     ap.add_argument("--t0", type=int, default=0)
     ap.add_argument("--seeds", type=int, default=8)
-    ap.add_argument("--distances", type=int, nargs="+", default=[1, 2, 3, 4])
+    ap.add_argument("--distances", type=int, nargs="*", default=[1, 2, 3, 4])
     ap.add_argument("--dim", type=int, default=3, choices=[3, 4])
     ap.add_argument("--eps", type=float, default=None, help="target standard error for N_total")
     ap.add_argument("--deflate", type=int, nargs="*", default=[],
                     help="numbers of low modes of Gamma5 D to deflate (each <= 48)")
     ap.add_argument("--defl-distances", type=int, nargs="*", default=[],
                     help="colouring distances also run with deflation")
+    ap.add_argument("--no-baselines", action="store_true",
+                    help="leave out the undeflated Hutchinson and dil12 rows")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     from synth.gauge import gauge_field
@@ -137,7 +139,7 @@ def main(argv=None):
     g = wdt.Gauge(lat, gauge_field(dims, a.eps_link, a.gauge_seed))
     rows = run(g, lat, a.m0, a.t0, range(a.seeds), a.distances, a.dim, a.eps,
                log=lambda s: print(s, flush=True), deflate=a.deflate,
-               defl_distances=a.defl_distances)
+               defl_distances=a.defl_distances, baselines=not a.no_baselines)
     if a.out:
         json.dump(dict(dims=list(dims), m0=a.m0, eps_link=a.eps_link, rows=rows), open(a.out, "w"),
                   indent=1)
