@@ -59,6 +59,22 @@ def exact_correlator(Dinv, dims, t, t0=0):
     return float(np.sum(np.abs(blk) ** 2))
 
 
+def exact_G(Dinv, dims, t):
+    """G(t) = (1/T) sum_t' tr[D^-1(t+t', t') Gamma5 D^-1(t', t+t') Gamma5] (Sec. 4,
+    eq. connected-results-G), time indices mod T, written out block by block."""
+    T = dims[3]
+    G5 = spin_colour(GAMMA5)
+    V = Dinv.shape[0] // 12
+    g5 = np.kron(np.eye(V // T), G5)  # Gamma5 on one time slice
+    tot = 0j
+    for tp in range(T):
+        a, b = slice_mask(dims, (t + tp) % T), slice_mask(dims, tp)
+        A = Dinv[np.ix_(a, b)]        # D^-1(t+t', t')
+        B = Dinv[np.ix_(b, a)]        # D^-1(t', t+t')
+        tot += np.trace(A @ g5 @ B @ g5)
+    return tot / T
+
+
 def sample_dot(v, x, dims=None, t=None, spin=None):
     """One sample sum conj(v) (B x) over the whole lattice or slice t.
 

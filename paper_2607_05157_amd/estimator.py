@@ -15,6 +15,10 @@ which batch and adds up the per-batch pieces the library returns.
   deflated (Sec. 2, eq. defl-split; see deflation.py): sources deflated before
   the solve, the contraction against the original sources, and the exact
   low-mode part added to every seed's estimate.
+- connected_correlator: G(t) = (1/T) sum_t' tr[D^-1(t+t',t') Gamma5
+  D^-1(t',t+t') Gamma5] (Sec. 4, eq. connected-results-G) = (1/T) sum_t'
+  ||D^-1(t+t', t')||_F^2 by gamma5-hermiticity, from spin-colour diluted
+  noise on every source slice t' (all-source-slice time dilution).
 - TraceLoss: f_k = eta_k^dag D(U, m0)^-1 eta_k as a torch.autograd.Function
   whose backward is the library's link force (d f / d U, d f / d m0).
 """
@@ -147,6 +151,42 @@ def probing_loop(gauge, lat, m0, n_c, sigma, t0, seeds, n_rhs=48, dilution=12, t
         out["correlator"] = C.mean(axis=0)
         out["correlator_per_seed"] = C
     return out
+
+
+def connected_correlator(gauge, lat, m0, seeds, t_sources=None, n_rhs=48, tol=1e-10,
+                         prec=wdt.FP16, inner_tol=0.005):
+    """G(t) of eq. connected-results-G with the (1/T) sum over source slices.
+
+    For every source slice t' and seed, the 12 spin-colour components of a
+    Rademacher vector on t' are solved; sum_k ||x_k(t)||^2 estimates
+    ||D^-1(t, t')||_F^2 (unbiased: the noise has unit variance and the
+    dilution removes the cross terms inside a site), and G(t) averages
+    t -> t + t' over the source slices.  t_sources defaults to every slice.
+    Returns dict(G=[T] mean over seeds, per_seed=[S, T], var=[T], stats)."""
+    T = lat.dims[3]
+    ts = list(range(T)) if t_sources is None else list(t_sources)
+    jobs = [(tp, s, k) for tp in ts for s in seeds for k in range(12)]
+    acc = {s: np.zeros(T) for s in seeds}
+    stats = []
+    for lo in range(0, len(jobs), n_rhs):
+        batch = jobs[lo:lo + n_rhs]
+        N = len(batch)
+        d = wdt.source_descs([s for (_, s, _) in batch], n_c=0,
+                             component=[k for (_, _, k) in batch],
+                             t0=[tp for (tp, _, _) in batch])
+        b = lat.new_batch(N)
+        wdt.sources(lat, d, b)
+        x = lat.new_batch(N)
+        _, st = wdt.solve(gauge, m0, b, x, N, tol=tol, prec=prec, inner_tol=inner_tol,
+                          max_iter=20000, max_outer=60)
+        stats.extend(st)
+        norms = wdt.contract(lat, None, x, N, mode=wdt.CONTRACT_NORM2)   # [N, T]
+        for i, (tp, s, _) in enumerate(batch):
+            acc[s] += np.roll(norms[i], -tp)          # entry t: ||x(t + t')||^2
+    per = np.array([acc[s] / len(ts) for s in seeds])
+    var = (np.sum((per - per.mean(axis=0)) ** 2, axis=0) / (len(seeds) - 1)
+           if len(seeds) > 1 else np.zeros(T))
+    return dict(G=per.mean(axis=0), per_seed=per, var=var, stats=stats, t_sources=ts)
 
 
 class TraceLoss:

@@ -130,6 +130,8 @@ def main(argv=None):
                     help="colouring distances also run with deflation")
     ap.add_argument("--no-baselines", action="store_true",
                     help="leave out the undeflated Hutchinson and dil12 rows")
+    ap.add_argument("--connected", action="store_true",
+                    help="also G(t) of eq. connected-results-G averaged over every source slice")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     from synth.gauge import gauge_field
@@ -140,9 +142,19 @@ def main(argv=None):
     rows = run(g, lat, a.m0, a.t0, range(a.seeds), a.distances, a.dim, a.eps,
                log=lambda s: print(s, flush=True), deflate=a.deflate,
                defl_distances=a.defl_distances, baselines=not a.no_baselines)
+    conn = None
+    if a.connected:
+        import torch
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        c = estimator.connected_correlator(g, lat, a.m0, list(range(a.seeds)))
+        torch.cuda.synchronize()
+        conn = dict(G=c["G"].tolist(), std_error=np.sqrt(c["var"] / a.seeds).tolist(),
+                    solves=len(c["stats"]), seconds=round(time.perf_counter() - t, 3))
+        print(json.dumps(dict(connected=conn)), flush=True)
     if a.out:
-        json.dump(dict(dims=list(dims), m0=a.m0, eps_link=a.eps_link, rows=rows), open(a.out, "w"),
-                  indent=1)
+        json.dump(dict(dims=list(dims), m0=a.m0, eps_link=a.eps_link, rows=rows, connected=conn),
+                  open(a.out, "w"), indent=1)
     return 0
 
 

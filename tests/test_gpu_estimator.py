@@ -218,3 +218,29 @@ def test_variance_study_matches_oracle():
         assert abs(row["variance"] - oest.sample_variance(ref)) <= 1e-9 * max(1.0, row["variance"])
         assert row["solves_per_sample"] == len(classes) * len(comps)
         assert row["n_total"] == row["solves_per_sample"] * max(1, int(np.ceil(row["variance"] / 0.25)))
+
+
+def test_connected_correlator_matches_oracle():
+    """G(t) with the average over all source slices (eq. connected-results-G):
+    per seed against the oracle's norms with the same noise, and the mean
+    within its error of the exact G(t)."""
+    dims, m0, seeds = (4, 4, 2, 6), 0.2, [0, 1, 2]
+    say("connected correlator", dims)
+    U = gauge_field(dims, 0.4, seed=12)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    out = E.connected_correlator(g, lat, m0, seeds, n_rhs=48, tol=1e-12, prec=W.FP64)
+    V, T = int(np.prod(dims)), dims[3]
+    Dinv = osolve.dense_inverse(dirac.dense_D(U, m0, dims, -1))
+    ref = np.zeros((len(seeds), T))
+    for a, s in enumerate(seeds):
+        for tp in range(T):
+            for k in range(12):
+                v = noise.probing_vector(dims, s, None, None, k, tp)
+                x = (Dinv @ v.ravel()).reshape(V, 12)
+                ref[a] += np.roll(oest.sample_norm2_per_t(x, dims), -tp)
+    ref /= T
+    assert np.max(np.abs(out["per_seed"] - ref)) < 1e-10 * np.max(ref)
+    exact = np.array([oest.exact_G(Dinv, dims, t).real for t in range(T)])
+    err = np.sqrt(out["var"] / len(seeds))
+    assert np.all(np.abs(out["G"] - exact) < 6 * err + 1e-10 * exact)

@@ -149,3 +149,21 @@ def test_time_diluted_correlator_estimator_unbiased_exact_limit():
             acc += estimator.sample_norm2_per_t(x, dims)
     for t in range(dims[3]):
         assert abs(acc[t] - estimator.exact_correlator(Dinv, dims, t, 0)) < 1e-12 * acc[t]
+
+
+def test_connected_G_is_average_of_slice_frobenius_norms():
+    """eq. connected-results-G written with Gamma5 equals (1/T) sum_t'
+    ||D^-1(t+t', t')||_F^2 (gamma5-hermiticity), and is real and positive."""
+    from oracle import dirac
+    from oracle.solve import dense_inverse
+    from synth.gauge import gauge_field
+    dims, m0 = (2, 2, 2, 6), 0.1
+    U = gauge_field(dims, 0.5, seed=3)
+    Dinv = dense_inverse(dirac.dense_D(U, m0, dims, -1))
+    T = dims[3]
+    for t in range(T):
+        g = estimator.exact_G(Dinv, dims, t)
+        ref = sum(estimator.exact_correlator(Dinv, dims, (t + tp) % T, tp) for tp in range(T)) / T
+        assert abs(g.imag) < 1e-12 * abs(g)
+        assert abs(g.real - ref) < 1e-12 * ref
+        assert ref > 0
