@@ -334,6 +334,7 @@ int make_plan(wdt_batch_s *b) {
         d.g = g->lat.geom();
         d.U = g->U64;
         d.diag = 4.0 + b->m0[i];
+        d.eo = (g->lat.even_odd_ok() && tuning().eo != 0) ? 1 : 0;
         vec_off[i] = off;
         off += ((size_t)6 * spinor_bytes(g->lat.V, N, WDT_FP64) + 255) / 256 * 256;
         part_off[i] = off;
