@@ -26,6 +26,9 @@
  *   WDT_FP16: [V][12][n_rhs] half2 (re, im) followed, in the same buffer, by
  *             [V][n_rhs] float scales; value = half * scale.  Use
  *             wdt_spinor_bytes for the size.
+ *   WDT_BF16: [V][12][n_rhs] bfloat16 pairs, one 32-bit word each (re in the
+ *             low 16 bits, im in the high 16 bits), no scale; the operator
+ *             computes in FP32 with FP32 links.
  *   The right-hand side index is innermost so that a site's SU(3) links are
  *   loaded once and reused across the batch.
  * Host links: double [V][4][3][3][2] = U_mu(x)[a][b] (re, im).
@@ -62,7 +65,7 @@ enum {
     WDT_ENODEVICE = -5      /* no usable gfx950 device */
 };
 
-enum { WDT_FP64 = 0, WDT_FP32 = 1, WDT_FP16 = 2 };
+enum { WDT_FP64 = 0, WDT_FP32 = 1, WDT_FP16 = 2, WDT_BF16 = 3 };
 
 typedef struct wdt_lattice_s *wdt_lattice;
 typedef struct wdt_gauge_s *wdt_gauge;
@@ -171,7 +174,11 @@ typedef struct {
     int32_t prec;        /* WDT_FP64, WDT_FP32 or WDT_FP16 */
     double inner_tol;    /* relative residual reduction per inner solve
                             (<= 0: 0.005); the last solve of a RHS stops
-                            earlier if that already meets tol */
+                            earlier if that already meets tol.  An inner
+                            solve also stops after 500 iterations, or for a
+                            RHS whose recurrence residual grows 1e4 times past
+                            its start; the FP64 correction continues from the
+                            true residual.  BF16 storage needs >= 0.05 */
     int32_t max_outer;   /* cap on defect-correction steps */
     int32_t x0_is_guess; /* 1: dev_x holds a starting guess */
     int32_t check_every; /* wdt_batch_solve: iterations between convergence

@@ -26,15 +26,16 @@ size_t spinor_bytes(int64_t V, int N, int prec) {
         case WDT_FP64: return (size_t)V * 12 * N * 16;
         case WDT_FP32: return (size_t)V * 12 * N * 8;
         case WDT_FP16: return (size_t)V * 12 * N * 4 + (size_t)V * N * 4;
+        case WDT_BF16: return (size_t)V * 12 * N * 4;
         default: return 0;
     }
 }
 
 size_t site_bytes(int prec) {
-    return prec == WDT_FP64 ? 192 : prec == WDT_FP32 ? 96 : 52;
+    return prec == WDT_FP64 ? 192 : prec == WDT_FP32 ? 96 : prec == WDT_BF16 ? 48 : 52;
 }
 size_t link_bytes(int prec) {
-    return prec == WDT_FP64 ? 144 : 72;  // FP32 links; FP16: two packed halves per element
+    return prec == WDT_FP64 ? 144 : 72;  // FP32 links (also BF16); FP16: two packed halves per element
 }
 
 // ---------------------------------------------------------------------------
@@ -231,7 +232,7 @@ int wdt_lattice_volume(wdt_lattice lat, int64_t *volume) {
 }
 
 int64_t wdt_spinor_bytes(wdt_lattice lat, int32_t n_rhs, int32_t prec) {
-    if (!lat || n_rhs < 1 || prec < WDT_FP64 || prec > WDT_FP16)
+    if (!lat || n_rhs < 1 || prec < WDT_FP64 || prec > WDT_BF16)
         return set_error(WDT_EINVAL, "wdt_spinor_bytes: bad argument");
     return (int64_t)spinor_bytes(lat->V, n_rhs, prec);
 }

@@ -163,26 +163,56 @@ __device__ __forceinline__ SiteNbr neighbours(const Geom &g, int s) {
 // ---------------------------------------------------------------------------
 // Spinor batch formats: [V][12][N] with the RHS index innermost.
 //  F64: double2; F32: float2; F16: __half2 plus a float scale per (site, rhs)
-//  stored after the V*12*N half2 values.
+//  stored after the V*12*N half2 values; B16: a bfloat16 pair, no scale.
 //  `link` is the element type of the links the operator reads; the FP16
 //  operator reads half links in a paired form made for half dot products.
+
+// bfloat16 pair (re in the low half, im in the high half of one 32-bit word):
+// the top 16 bits of an IEEE binary32, so decoding is a shift and encoding a
+// rounding of the low 16 bits (to nearest, ties to even; NaN stays NaN).
+struct bf16x2 {
+    unsigned int v;
+};
+__device__ __forceinline__ float bf16_lo(bf16x2 e) { return __uint_as_float(e.v << 16); }
+__device__ __forceinline__ float bf16_hi(bf16x2 e) { return __uint_as_float(e.v & 0xffff0000u); }
+__device__ __forceinline__ unsigned int bf16_bits(float f) {
+    const unsigned int u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (u >> 16) | 0x0040u;
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ bf16x2 bf16_pack(float re, float im) {
+    return bf16x2{bf16_bits(re) | (bf16_bits(im) << 16)};
+}
+
 struct F64 {
     using real = double;
     using elem = double2;
     using link = double2;
     static constexpr bool scaled = false;
+    static constexpr bool bf16 = false;
 };
 struct F32 {
     using real = float;
     using elem = float2;
     using link = float2;
     static constexpr bool scaled = false;
+    static constexpr bool bf16 = false;
 };
 struct F16 {
     using real = float;
     using elem = __half2;
     using link = __half2;  // two per link element: (ur, -ui), (ui, ur)
     static constexpr bool scaled = true;
+    static constexpr bool bf16 = false;
+};
+// bfloat16 storage (FP32's exponent range, so no scale), FP32 arithmetic and
+// the FP32 links
+struct B16 {
+    using real = float;
+    using elem = bf16x2;
+    using link = float2;
+    static constexpr bool scaled = false;
+    static constexpr bool bf16 = true;
 };
 
 template <class S> struct SpinorPtr {
@@ -220,6 +250,13 @@ __device__ __forceinline__ typename S::real load_site_raw(const SpinorPtr<S> &sp
             v[k] = {f.x, f.y};
         }
         return sp.scale[(size_t)site * N + r];
+    } else if constexpr (S::bf16) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const bf16x2 e = q[k * N];
+            v[k] = {bf16_lo(e), bf16_hi(e)};
+        }
+        return typename S::real(1);
     } else {
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
@@ -251,6 +288,8 @@ __device__ __forceinline__ void elems_to_cplx(const typename S::elem (&e)[12],
         if constexpr (S::scaled) {
             const float2 f = __half22float2(e[k]);
             v[k] = {f.x, f.y};
+        } else if constexpr (S::bf16) {
+            v[k] = {bf16_lo(e[k]), bf16_hi(e[k])};
         } else {
             v[k] = {e[k].x, e[k].y};
         }
@@ -274,6 +313,12 @@ __device__ __forceinline__ void load_site_once(const SpinorPtr<S> &sp, int site,
             __builtin_memcpy(&h, &u, 4);
             const float2 f = __half22float2(h);
             v[k] = {f.x * sc, f.y * sc};
+        }
+    } else if constexpr (S::bf16) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const bf16x2 e{__builtin_nontemporal_load(&q[k * N].v)};
+            v[k] = {bf16_lo(e), bf16_hi(e)};
         }
     } else {
 #pragma unroll
@@ -323,6 +368,13 @@ __device__ __forceinline__ void store_site(const SpinorPtr<S> &sp, int site, int
             __builtin_nontemporal_store(m, sp.scale + (size_t)site * N + r);
         else
             sp.scale[(size_t)site * N + r] = m;
+    } else if constexpr (S::bf16) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const bf16x2 e = bf16_pack(v[k].re, v[k].im);
+            if constexpr (STREAM) __builtin_nontemporal_store(e.v, &sp.p[base + k * N].v);
+            else sp.p[base + k * N] = e;
+        }
     } else {
         using E = typename S::elem;
 #pragma unroll

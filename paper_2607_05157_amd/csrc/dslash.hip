@@ -60,7 +60,10 @@ __global__ __launch_bounds__(256) void k_dslash_march(Geom g, const typename S::
 static int nc_of(int N) { return (N == 48 || N == 64 || N == 16) ? N : 0; }
 
 template <class S> static int prec_of() {
-    return std::is_same<S, F64>::value ? WDT_FP64 : std::is_same<S, F32>::value ? WDT_FP32 : WDT_FP16;
+    return std::is_same<S, F64>::value   ? WDT_FP64
+           : std::is_same<S, F32>::value ? WDT_FP32
+           : std::is_same<S, B16>::value ? WDT_BF16
+                                         : WDT_FP16;
 }
 
 template <class S>
@@ -143,9 +146,10 @@ static int launch_t(const wdt_gauge_s *gf, const HopSpec &hs, const void *in, vo
     // timing classes: the whole-lattice operator, one-parity pure hops, and
     // one-parity launches with the site's own term (the even-odd operator's
     // second half, residuals, reconstruction)
-    static const char *names[3][3] = {{"dslash_fp64", "dslash_fp32", "dslash_fp16"},
-                                      {"dslash_hop_fp64", "dslash_hop_fp32", "dslash_hop_fp16"},
-                                      {"dslash_eo_fp64", "dslash_eo_fp32", "dslash_eo_fp16"}};
+    static const char *names[3][4] = {
+        {"dslash_fp64", "dslash_fp32", "dslash_fp16", "dslash_bf16"},
+        {"dslash_hop_fp64", "dslash_hop_fp32", "dslash_hop_fp16", "dslash_hop_bf16"},
+        {"dslash_eo_fp64", "dslash_eo_fp32", "dslash_eo_fp16", "dslash_eo_bf16"}};
     const int kind = hs.parity < 0 ? 0 : hs.cs == 0.0 ? 1 : 2;
     // algorithmic bytes: in, out, a separate self, the epilogue's vector, links once
     const int nvec = 2 + ((hs.cs != 0.0 && hs.self && hs.self != in) ? 1 : 0) +
@@ -208,6 +212,8 @@ int launch_hop(const wdt_gauge_s *g, int prec, int dagger, int epi, const HopSpe
             return launch_p<F32>(g, hs, dagger, epi, in, out, aux, N, partials, sh, stream, g->U32);
         case WDT_FP16:
             return launch_p<F16>(g, hs, dagger, epi, in, out, aux, N, partials, sh, stream, g->U16);
+        case WDT_BF16:
+            return launch_p<B16>(g, hs, dagger, epi, in, out, aux, N, partials, sh, stream, g->U32);
         default:
             return set_error(WDT_EINVAL, "bad precision %d", prec);
     }
@@ -266,6 +272,7 @@ int op_blocks_per_cu(int prec, int N, int threads, int mode) {
     if (it != cache.end()) return it->second;
     const int nb = prec == WDT_FP64   ? occ_p<F64>(N, threads, mode)
                    : prec == WDT_FP32 ? occ_p<F32>(N, threads, mode)
+                   : prec == WDT_BF16 ? occ_p<B16>(N, threads, mode)
                                       : occ_p<F16>(N, threads, mode);
     cache[key] = nb;
     return nb;
@@ -280,7 +287,7 @@ extern "C" int wdt_apply_D(wdt_gauge g, double m0, const void *dev_in, void *dev
     WDT_CHECK(dev_in != nullptr && dev_out != nullptr, "wdt_apply_D: null vector");
     WDT_CHECK(dev_in != dev_out, "wdt_apply_D: input and output must not overlap");
     WDT_CHECK(n_rhs >= 1, "wdt_apply_D: n_rhs must be >= 1 (got %d)", n_rhs);
-    WDT_CHECK(prec >= WDT_FP64 && prec <= WDT_FP16, "wdt_apply_D: bad precision %d", prec);
+    WDT_CHECK(prec >= WDT_FP64 && prec <= WDT_BF16, "wdt_apply_D: bad precision %d", prec);
     WDT_CHECK(dagger == 0 || dagger == 1, "wdt_apply_D: dagger must be 0 or 1");
     const Shape sh = site_shape(g->lat, n_rhs, prec);
     return launch_dslash(g, m0, prec, dagger, EPI_NONE, dev_in, dev_out, nullptr, n_rhs, nullptr,

@@ -368,7 +368,7 @@ int wdt_colouring_check(const int32_t *dims, int32_t nD, int32_t d, int32_t n_c,
 int wdt_sources(wdt_lattice lat, const wdt_source_desc *desc, int32_t n_rhs, void *dev_out,
                 int32_t prec, void *stream) {
     WDT_CHECK(lat && desc && dev_out && n_rhs >= 1, "wdt_sources: bad argument");
-    WDT_CHECK(prec >= WDT_FP64 && prec <= WDT_FP16, "wdt_sources: bad precision");
+    WDT_CHECK(prec >= WDT_FP64 && prec <= WDT_BF16, "wdt_sources: bad precision");
     for (int r = 0; r < n_rhs; ++r) {
         WDT_CHECK(desc[r].seed < (1ull << 24), "wdt_sources: seed %llu must be < 2^24",
                   (unsigned long long)desc[r].seed);
@@ -396,6 +396,10 @@ int wdt_sources(wdt_lattice lat, const wdt_source_desc *desc, int32_t n_rhs, voi
         case WDT_FP32:
             hipLaunchKernelGGL(k_sources<F32>, grid, dim3(sh.threads), 0, st, g, dd, n_rhs, NT,
                                sh.SB, make_spinor<F32>(dev_out, g.V, n_rhs));
+            break;
+        case WDT_BF16:
+            hipLaunchKernelGGL(k_sources<B16>, grid, dim3(sh.threads), 0, st, g, dd, n_rhs, NT,
+                               sh.SB, make_spinor<B16>(dev_out, g.V, n_rhs));
             break;
         default:
             hipLaunchKernelGGL(k_sources<F16>, grid, dim3(sh.threads), 0, st, g, dd, n_rhs, NT,

@@ -11,7 +11,7 @@ struct RhsState {
     double2 rv;  // rhat^dag v of the current iteration (fused updates)
     double rr, bb, tol2;
     int active;  // 1 while the RHS is iterating
-    int flag;    // 0 running, 1 converged, 2 breakdown
+    int flag;    // 0 running, 1 converged, 2 breakdown, 3 diverged (inner solves)
     int iters;
     int pad;
 };
@@ -316,6 +316,11 @@ __device__ __forceinline__ void scalar_check_body(RhsState *st, const double2 *p
             } else if (!isfinite(rr.x)) {
                 s.active = 0;
                 s.flag = 2;
+            } else if (s.active && rr.x > 1e8 * s.bb) {
+                // the low-precision recurrence has run away (its residual is
+                // 1e4 times the start): stop, the outer correction takes over
+                s.active = 0;
+                s.flag = 3;
             }
         }
         st[r] = s;

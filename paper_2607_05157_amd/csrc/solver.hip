@@ -483,10 +483,13 @@ int bicgstab_iterate(Bicg &B, int prec, void *x, void *r, void *rhat, void *p, v
     // p = r
     WDT_HIP(hipMemcpyAsync(p, r, spinor_bytes(V, N, prec), hipMemcpyDeviceToDevice, B.stream));
     const double vb = (double)B.geo.nsites * N * site_bytes(prec);  // one vector pass
-    static const char *nm_s[3] = {"axpy_s_fp64", "axpy_s_fp32", "axpy_s_fp16"};
-    static const char *nm_xr[3] = {"update_xr_fp64", "update_xr_fp32", "update_xr_fp16"};
-    static const char *nm_p[3] = {"update_p_fp64", "update_p_fp32", "update_p_fp16"};
-    static const char *nm_xrp[3] = {"update_xrp_fp64", "update_xrp_fp32", "update_xrp_fp16"};
+    static const char *nm_s[4] = {"axpy_s_fp64", "axpy_s_fp32", "axpy_s_fp16", "axpy_s_bf16"};
+    static const char *nm_xr[4] = {"update_xr_fp64", "update_xr_fp32", "update_xr_fp16",
+                                   "update_xr_bf16"};
+    static const char *nm_p[4] = {"update_p_fp64", "update_p_fp32", "update_p_fp16",
+                                  "update_p_bf16"};
+    static const char *nm_xrp[4] = {"update_xrp_fp64", "update_xrp_fp32", "update_xrp_fp16",
+                                    "update_xrp_bf16"};
     // the inner solves of the mixed solver take the fused end of iteration
     constexpr bool fused = !std::is_same<S, F64>::value;
     EventGuard ev[2];
@@ -646,6 +649,9 @@ static int solve_fp64(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
 }
 
 // FP64 defect correction around an inner solve in storage S (F32 or F16).
+// Iterations one inner solve of the defect correction may take.
+constexpr int kInnerCap = 500;
+
 template <class S>
 static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N, int prec,
                        const wdt_solve_params &P, wdt_rhs_stats *stats, hipStream_t stream) {
@@ -786,7 +792,10 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
         WDT_HIP(hipStreamSynchronize(stream));
         for (int k = 0; k < N; ++k) before[k] = hs[k].iters;
         int done = 0;
-        WDT_TRY(bicgstab_iterate<S>(B, prec, e, rS, rhat, p, v, s, t, budget, &done));
+        // an inner solve that stops converging in low precision would spend the
+        // whole budget; each one gets at most kInnerCap iterations
+        WDT_TRY(bicgstab_iterate<S>(B, prec, e, rS, rhat, p, v, s, t, std::min(budget, kInnerCap),
+                                    &done));
         WDT_HIP(hipMemcpyAsync(hs.data(), B.st, sizeof(RhsState) * N, hipMemcpyDeviceToHost, stream));
         WDT_HIP(hipStreamSynchronize(stream));
         for (int k = 0; k < N; ++k) total_it[k] += hs[k].iters - before[k];
@@ -821,6 +830,8 @@ extern "C" int wdt_solve(wdt_gauge g, double m0, const void *dev_b, void *dev_x,
             return solve_mixed<F32>(g, m0, dev_b, dev_x, n_rhs, WDT_FP32, *params, stats, st);
         case WDT_FP16:
             return solve_mixed<F16>(g, m0, dev_b, dev_x, n_rhs, WDT_FP16, *params, stats, st);
+        case WDT_BF16:
+            return solve_mixed<B16>(g, m0, dev_b, dev_x, n_rhs, WDT_BF16, *params, stats, st);
         default:
             return set_error(WDT_EINVAL, "wdt_solve: bad precision %d", params->prec);
     }

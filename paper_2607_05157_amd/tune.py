@@ -21,8 +21,8 @@ if __name__ == "__main__":
     import os
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
-SITE_BYTES = {0: 192, 1: 96, 2: 52}
-LINK_BYTES = {0: 144, 1: 72, 2: 72}  # FP32 links; FP16: two packed halves per element
+SITE_BYTES = {0: 192, 1: 96, 2: 52, 3: 48}
+LINK_BYTES = {0: 144, 1: 72, 2: 72, 3: 72}  # FP32 links (also BF16); FP16: two packed halves
 
 
 def alg_bytes(V, N, prec):

@@ -16,9 +16,10 @@ LIB_PATH = os.environ.get("WDT_LIB") or os.path.join(HERE, "libwdt.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "wdt.h")
 
 OK, WNOTCONVERGED, EINVAL, ENOMEM, EHIP, ESEARCH, ENODEVICE = 0, 1, -1, -2, -3, -4, -5
-FP64, FP32, FP16 = 0, 1, 2
+FP64, FP32, FP16, BF16 = 0, 1, 2, 3
 CONTRACT_DOT, CONTRACT_NORM2 = 0, 1
-PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "mixed_fp16": FP16, "mixed_fp32": FP32}
+PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16, "mixed_fp16": FP16,
+        "mixed_fp32": FP32, "mixed_bf16": BF16}
 
 
 class SourceDesc(ctypes.Structure):

@@ -610,3 +610,86 @@ def test_even_odd_solves_match_full_system(c1, N):
             assert its[1] < its[0], (prec, its)
     finally:
         W.set_launch_shape()
+
+
+def bf16_bits(a):
+    """float32 array -> bfloat16 bit patterns (round to nearest, ties to even)."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint32)
+
+
+def bf16_batch(psi):
+    """[V, 12, N] complex -> device BF16 batch (one 32-bit word per complex:
+    re in the low half, im in the high half) and the rounded values."""
+    lo, hi = bf16_bits(psi.real), bf16_bits(psi.imag)
+    words = (lo | (hi << 16)).astype(np.uint32)
+    return torch.from_numpy(words.view(np.int32).copy()).cuda(), from_bf16_words(words)
+
+
+def from_bf16_words(w):
+    w = np.asarray(w, dtype=np.uint32)
+    re = (w << 16).view(np.float32).astype(np.float64)
+    im = (w & 0xFFFF0000).view(np.float32).astype(np.float64)
+    return re + 1j * im
+
+
+@pytest.mark.parametrize("N", [20, 48])
+def test_bf16_operator_sources_and_mixed_solve(c1, N):
+    """BF16 storage: sources exact, the operator (FP32 arithmetic, FP32 links,
+    sweep and one-site-per-wavefront shapes, dagger) against the oracle on the
+    BF16-rounded input within the output's rounding, and a mixed BF16 solve
+    refined to 1e-10 against dense LU within 1e-8."""
+    dims = (4, 4, 2, 6)
+    say("bf16", N)
+    V = int(np.prod(dims))
+    U = gauge_field(dims, 0.5, seed=14)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    # sources: +-1 and 0 are exact in BF16
+    xs = torch.zeros(V * 12 * N, dtype=torch.int32, device="cuda")
+    W.sources(lat, W.source_descs(list(range(N))), xs, prec=W.BF16)
+    ref_src = lat.new_batch(N)
+    W.sources(lat, W.source_descs(list(range(N))), ref_src)
+    got = from_bf16_words(xs.cpu().numpy().view(np.uint32)).reshape(V, 12, N)
+    assert np.array_equal(got, ref_src.cpu().numpy())
+    psi = rand_batch(V, N, 6)
+    x, psi_r = bf16_batch(psi)
+    psi_r = psi_r.reshape(V, 12, N)
+    for dagger in (False, True):
+        ref = dirac.apply_D(U, 0.05, psi_r, dims, -1, dagger=dagger)
+        out = torch.zeros_like(x)
+        W.apply_D(g, 0.05, x, out, N, W.BF16, dagger)
+        res = from_bf16_words(out.cpu().numpy().view(np.uint32)).reshape(V, 12, N)
+        err = np.max(np.abs(res - ref) / (np.abs(ref) + 1e-3 * np.max(np.abs(ref))))
+        assert err < 2 ** -8, (dagger, err)
+    dims1, m0, U1, Dinv = c1
+    lat1 = W.Lattice(dims1, -1)
+    g1 = W.Gauge(lat1, U1)
+    b = lat1.new_batch(N)
+    W.sources(lat1, W.source_descs(list(range(N))), b)
+    xx = lat1.new_batch(N)
+    rc, st = W.solve(g1, m0, b, xx, N, tol=1e-10, prec=W.BF16, inner_tol=0.02)
+    assert rc == W.OK and all(s["converged"] for s in st)
+    X = Dinv @ b.cpu().numpy().reshape(-1, N)
+    xs_ = xx.cpu().numpy().reshape(-1, N)
+    assert np.max(np.linalg.norm(xs_ - X, axis=0) / np.linalg.norm(X, axis=0)) < 1e-8
+
+
+def test_low_precision_inner_solve_that_cannot_converge_is_contained(c1):
+    """A BF16 inner tolerance below what BF16 storage can reach: the inner
+    solves stop (iteration cap, runaway guard) instead of spending the whole
+    budget, and the FP64 defect correction still reaches 1e-10 or reports
+    WNOTCONVERGED with a finite, bounded residual."""
+    dims, m0, U, Dinv = c1
+    say("bf16 inner tolerance too tight")
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    N = 16
+    b = lat.new_batch(N)
+    W.sources(lat, W.source_descs(list(range(N))), b)
+    x = lat.new_batch(N)
+    rc, st = W.solve(g, m0, b, x, N, tol=1e-10, prec=W.BF16, inner_tol=1e-4, max_iter=4000,
+                     max_outer=12, allow_unconverged=True)
+    assert all(np.isfinite(s["true_residual"]) for s in st)
+    assert max(s["true_residual"] for s in st) < 1.0
+    assert max(s["iterations"] for s in st) <= 12 * 500
