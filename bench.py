@@ -144,6 +144,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--bf16-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--inner-tol", type=float, default=0.005)
     ap.add_argument("--no-batched", action="store_true")
@@ -209,6 +210,22 @@ def main():
     t_mixed = (time.perf_counter() - t_start) / args.steps
     prof = wdt.profile_read()
     wdt.profile(False)
+
+    # the same steps with BF16 storage (inner tolerance 0.05: BF16 keeps 8
+    # mantissa bits), for the record
+    t_bf16 = None
+    if args.bf16_steps > 0:
+        log("bf16 steps", args.bf16_steps, "after one warm-up step")
+        for k in range(args.bf16_steps + 1):
+            if k == 1:
+                torch.cuda.synchronize()
+                t0_ = time.perf_counter()
+            wdt.sources(lat, descs(present[k % len(present)]), b)
+            wdt.solve(g, m0, b, x, N, tol=cfg["tol"], prec=wdt.BF16, inner_tol=0.05,
+                      max_iter=20000, max_outer=60)
+            wdt.contract(lat, b, x, N, spin=G5)
+        torch.cuda.synchronize()
+        t_bf16 = (time.perf_counter() - t0_) / args.bf16_steps
 
     log("fp64 steps", args.fp64_steps)
     torch.cuda.synchronize()
@@ -281,6 +298,8 @@ def main():
                      "traffic": traffic,
                      "traffic_over_algorithmic": round(traffic / per_launch_b, 3) if traffic else None},
         "seconds_per_trace": {"mixed": round(t_mixed * len(present), 3),
+                              "mixed_bf16_storage": (round(t_bf16 * len(present), 3)
+                                                     if t_bf16 else None),
                               "fp64": round(t_fp64 * len(present), 3) if st64 else None,
                               "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3) if st64 else None},
         "fp64_dslash_gbps": round(d64["gbps"], 1) if d64 else None,
