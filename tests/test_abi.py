@@ -42,6 +42,7 @@ def test_lattice_argument_validation():
     assert lat.V == 384
     assert lat.spinor_bytes(3, wdt.FP64) == 384 * 12 * 3 * 16
     assert lat.spinor_bytes(3, wdt.FP16) == 384 * 12 * 3 * 4 + 384 * 3 * 4
+    assert lat.spinor_bytes(3, wdt.BF16) == 384 * 12 * 3 * 4
     with pytest.raises(wdt.WdtError):
         lat.spinor_bytes(0, wdt.FP64)
 
