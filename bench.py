@@ -37,8 +37,8 @@ HBM_PEAK_GBPS = 8000.0
 # They describe the sources they were taken on and are reported only while
 # those sources are unchanged.
 OPERATOR_SOURCES = ["kernels.h", "device.h", "dslash.hip", "solver.hip", "internal.h"]
-MEASURED_TRAFFIC = {"sources": "2e4b6085d179088a",
-                    "dslash_eo_fp16": 1114.4e6, "dslash_hop_fp16": 840.6e6}
+MEASURED_TRAFFIC = {"sources": "4bf03d26f6d9a714",
+                    "dslash_eo_fp16": 1113.9e6, "dslash_hop_fp16": 836.9e6}
 
 
 def operator_sources_hash():
@@ -145,6 +145,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--bf16-steps", type=int, default=2)
+    ap.add_argument("--clover-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--inner-tol", type=float, default=0.005)
     ap.add_argument("--no-batched", action="store_true")
@@ -227,6 +228,35 @@ def main():
         torch.cuda.synchronize()
         t_bf16 = (time.perf_counter() - t0_) / args.bf16_steps
 
+    # the same steps with the clover term (c_sw = 1, its tree-level value) on
+    # the operator: no even-odd preconditioning then, for the record
+    t_clov, clov = None, None
+    if args.clover_steps > 0:
+        log("clover steps", args.clover_steps, "after one warm-up step")
+        gc = wdt.Gauge(lat, U)
+        gc.set_clover(1.0)
+        its = []
+        for k in range(args.clover_steps + 1):
+            if k == 1:
+                torch.cuda.synchronize()
+                wdt.profile(True)
+                t0_ = time.perf_counter()
+            wdt.sources(lat, descs(present[k % len(present)]), b)
+            rc_, st_ = wdt.solve(gc, m0, b, x, N, tol=cfg["tol"], prec=wdt.FP16,
+                                 inner_tol=args.inner_tol, max_iter=20000, max_outer=60)
+            wdt.contract(lat, b, x, N, spin=G5)
+            if k >= 1:
+                its += [s_["iterations"] for s_ in st_]
+        torch.cuda.synchronize()
+        t_clov = (time.perf_counter() - t0_) / args.clover_steps
+        pc = wdt.profile_read()
+        wdt.profile(False)
+        del gc
+        op = pc.get("dslash_fp16")
+        clov = {"csw": 1.0, "iterations_max": max(its),
+                "dslash_fp16_clover_gbps": round(op["gbps"], 1) if op else None,
+                "dslash_fp16_clover_calls": op["calls"] if op else None}
+
     log("fp64 steps", args.fp64_steps)
     torch.cuda.synchronize()
     t0_ = time.perf_counter()
@@ -300,9 +330,12 @@ def main():
         "seconds_per_trace": {"mixed": round(t_mixed * len(present), 3),
                               "mixed_bf16_storage": (round(t_bf16 * len(present), 3)
                                                      if t_bf16 else None),
+                              "mixed_clover": (round(t_clov * len(present), 3)
+                                               if t_clov else None),
                               "fp64": round(t_fp64 * len(present), 3) if st64 else None,
                               "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3) if st64 else None},
         "fp64_dslash_gbps": round(d64["gbps"], 1) if d64 else None,
+        "clover_operator": clov,
         "kernels_mixed": {k: {"calls": v["calls"], "ms": round(v["ms"], 3),
                               "gbps": round(v["gbps"], 1)} for k, v in prof.items()},
         "kernels_fp64": {k: {"calls": v["calls"], "ms": round(v["ms"], 3),

@@ -102,6 +102,37 @@ int wdt_gauge_destroy(wdt_gauge g);
 int wdt_gauge_get(wdt_gauge g, double *host_links);
 
 /*
+ * Clover (Sheikholeslami-Wohlert) term for ensembles generated with the
+ * O(a)-improved Wilson action; the paper's operator (Sec. 1) is the plain
+ * Wilson one, which csw = 0 gives back.  With csw != 0 every later
+ * application of D on this gauge (wdt_apply_D, wdt_solve, the batched solver
+ * and the estimators built on them) adds to the site's own term
+ *   C(x) = -(csw / 2) sum_{mu < nu} sigma_{mu nu} F_{mu nu}(x),
+ * sigma_{mu nu} = (i/2) [gamma_mu, gamma_nu] (DeGrand-Rossi basis) and
+ * F = (Q - Q^dag) / (8i), Q_{mu nu}(x) the sum of the four plaquettes of the
+ * (mu, nu) plane that start and end at x in the same sense (periodic in every
+ * direction; the fermion time-boundary factor is not part of these loops; F
+ * keeps its colour trace).  C is Hermitian and commutes with gamma5, so
+ * D^dag = gamma5 D gamma5 still holds.
+ *
+ * wdt_gauge_set_clover builds C from the FP64 links (FP64, plus an FP32 copy
+ * for the FP32 / FP16 / BF16 operators: 72 * 12 bytes per site of device
+ * memory, allocated on the first call).  csw = 0 frees it.  Synchronous.
+ * While a clover term is set, solves run without even-odd preconditioning
+ * (the Schur form would need the inverse odd-site blocks) and wdt_force
+ * returns WDT_EINVAL (the term's derivative is not implemented).
+ * WDT_EINVAL for a null handle or a non-finite csw.
+ *
+ * wdt_gauge_get_clover copies C to host_packed (host, V * 72 doubles): per
+ * site the two chiral 6 x 6 blocks (spins 0-1, then 2-3; index 3 * spin +
+ * colour inside a block, C being zero between them), each as its 6 real
+ * diagonal elements followed by the 15 elements above the diagonal, row by
+ * row, as (re, im) pairs.  WDT_EINVAL when the gauge has no clover term.
+ */
+int wdt_gauge_set_clover(wdt_gauge g, double csw);
+int wdt_gauge_get_clover(wdt_gauge g, double *host_packed);
+
+/*
  * Torus colouring (Sec. 3, eq. coloring-formula): c(x) = sum_j sigma_j x_j
  * mod n_c, valid at distance d when distinct sites within periodic L1
  * distance d (wrap-around included) get different colours.  Exhaustive

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libwdt.so")
-SOURCES = ["api.hip", "dslash.hip", "solver.hip", "estimator.hip", "batch.hip", "block.hip"]
+SOURCES = ["api.hip", "dslash.hip", "solver.hip", "estimator.hip", "batch.hip", "block.hip", "clover.hip"]
 ARCH = os.environ.get("WDT_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

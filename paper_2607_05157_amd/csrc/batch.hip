@@ -13,8 +13,8 @@
 // ones get none), which only rewrites the device-side system table between
 // graph replays.
 //
-// Systems whose lattice has every extent even are solved even-odd
-// preconditioned, like the single-system solver: the iteration runs on the
+// Systems whose lattice has every extent even (and no clover term) are
+// solved even-odd preconditioned, like the single-system solver: the iteration runs on the
 // even sites with M = a - H_eo H_oe / (4a) (a = 4 + m0), the restart turns the
 // true residual into the Schur right-hand side, and the odd sites of x are
 // rebuilt from b and the even sites at the end of every round.
@@ -32,6 +32,7 @@ enum VecId { V_X = 0, V_B, V_R, V_RHAT, V_P, V_V, V_S, V_T, V_COUNT };
 struct SysDesc {
     Geom g;
     const double2 *U;
+    const double *C;  // clover term or null (then eo = 0)
     double diag;
     int eo;  // 1: even-odd preconditioned (every extent even)
     int N, NT, SB, tiles, G;
@@ -87,9 +88,14 @@ template <int EPI>
 __global__ __launch_bounds__(256) void kb_dslash(const SysDesc *sys, int nsys, int in, int out,
                                                  int aux) {
     WDT_SYS_CTX
-    dslash_body<F64, 0, false, EPI>(d.g, d.U, sp(in), d.diag, -0.5, sp(in), sp(out),
-                                    sp(aux >= 0 ? aux : in),
-                                    d.N, d.NT, d.SB, d.part, tile, tile + 1, lb, d.G);
+    if (d.C)
+        dslash_body<F64, 0, false, EPI, false, true>(d.g, d.U, d.C, sp(in), d.diag, -0.5, sp(in),
+                                                     sp(out), sp(aux >= 0 ? aux : in), d.N, d.NT,
+                                                     d.SB, d.part, tile, tile + 1, lb, d.G);
+    else
+        dslash_body<F64, 0, false, EPI>(d.g, d.U, nullptr, sp(in), d.diag, -0.5, sp(in), sp(out),
+                                        sp(aux >= 0 ? aux : in),
+                                        d.N, d.NT, d.SB, d.part, tile, tile + 1, lb, d.G);
 }
 
 // The iteration's operator, first half: even-odd systems put H_oe in on the
@@ -97,7 +103,7 @@ __global__ __launch_bounds__(256) void kb_dslash(const SysDesc *sys, int nsys, i
 __global__ __launch_bounds__(256) void kb_op_odd(const SysDesc *sys, int nsys, int in, int out) {
     WDT_SYS_CTX
     if (!d.eo) return;
-    dslash_body<F64, 0, false, EPI_NONE>(sys_geom(d, 1), d.U, sp(in), 0.0, 1.0, sp(in), sp(out),
+    dslash_body<F64, 0, false, EPI_NONE>(sys_geom(d, 1), d.U, nullptr, sp(in), 0.0, 1.0, sp(in), sp(out),
                                          sp(in), d.N, d.NT, d.SB, nullptr, tile, tile + 1, lb,
                                          d.G);
 }
@@ -110,12 +116,16 @@ __global__ __launch_bounds__(256) void kb_op_even(const SysDesc *sys, int nsys, 
     WDT_SYS_CTX
     const SpinorPtr<F64> pa = sp(aux >= 0 ? aux : in);
     if (d.eo)
-        dslash_body<F64, 0, false, EPI>(sys_geom(d, 0), d.U, sp(in), d.diag,
+        dslash_body<F64, 0, false, EPI>(sys_geom(d, 0), d.U, nullptr, sp(in), d.diag,
                                         -0.25 / d.diag, sp(out), sp(out), pa, d.N, d.NT, d.SB,
                                         d.part, tile, tile + 1, lb, d.G);
+    else if (d.C)
+        dslash_body<F64, 0, false, EPI, false, true>(d.g, d.U, d.C, sp(in), d.diag, -0.5, sp(in),
+                                                     sp(out), pa, d.N, d.NT, d.SB, d.part, tile,
+                                                     tile + 1, lb, d.G);
     else
-        dslash_body<F64, 0, false, EPI>(d.g, d.U, sp(in), d.diag, -0.5, sp(in), sp(out), pa, d.N,
-                                        d.NT, d.SB, d.part, tile, tile + 1, lb, d.G);
+        dslash_body<F64, 0, false, EPI>(d.g, d.U, nullptr, sp(in), d.diag, -0.5, sp(in), sp(out),
+                                        pa, d.N, d.NT, d.SB, d.part, tile, tile + 1, lb, d.G);
 }
 
 // Even-odd systems: r_e += H_eo r_o / (2a) in place (the Schur right-hand
@@ -123,7 +133,7 @@ __global__ __launch_bounds__(256) void kb_op_even(const SysDesc *sys, int nsys, 
 __global__ __launch_bounds__(256) void kb_schur_rhs(const SysDesc *sys, int nsys) {
     WDT_SYS_CTX
     if (!d.eo) return;
-    dslash_body<F64, 0, false, EPI_NORM>(sys_geom(d, 0), d.U, sp(V_R), 1.0, 0.5 / d.diag,
+    dslash_body<F64, 0, false, EPI_NORM>(sys_geom(d, 0), d.U, nullptr, sp(V_R), 1.0, 0.5 / d.diag,
                                          sp(V_R), sp(V_R), sp(V_R), d.N, d.NT, d.SB, d.part,
                                          tile, tile + 1, lb, d.G);
 }
@@ -132,7 +142,7 @@ __global__ __launch_bounds__(256) void kb_schur_rhs(const SysDesc *sys, int nsys
 __global__ __launch_bounds__(256) void kb_schur_odd(const SysDesc *sys, int nsys) {
     WDT_SYS_CTX
     if (!d.eo) return;
-    dslash_body<F64, 0, false, EPI_NONE>(sys_geom(d, 1), d.U, sp(V_B), 1.0 / d.diag,
+    dslash_body<F64, 0, false, EPI_NONE>(sys_geom(d, 1), d.U, nullptr, sp(V_B), 1.0 / d.diag,
                                          0.5 / d.diag, sp(V_X), sp(V_X), sp(V_X), d.N, d.NT,
                                          d.SB, nullptr, tile, tile + 1, lb, d.G);
 }
@@ -333,8 +343,9 @@ int make_plan(wdt_batch_s *b) {
         rhs += N;
         d.g = g->lat.geom();
         d.U = g->U64;
+        d.C = g->C64;
         d.diag = 4.0 + b->m0[i];
-        d.eo = (g->lat.even_odd_ok() && tuning().eo != 0) ? 1 : 0;
+        d.eo = (g->lat.even_odd_ok() && tuning().eo != 0 && !g->C64) ? 1 : 0;
         vec_off[i] = off;
         off += ((size_t)6 * spinor_bytes(g->lat.V, N, WDT_FP64) + 255) / 256 * 256;
         part_off[i] = off;
@@ -529,7 +540,8 @@ int wdt_batch_solve(wdt_batch b, void *const *dev_b, void *const *dev_x,
         WDT_CHECK(dev_b[i] && dev_x[i] && dev_b[i] != dev_x[i], "wdt_batch_solve: system %d", i);
         b->host[i].vec[V_B] = (double2 *)dev_b[i];
         b->host[i].vec[V_X] = (double2 *)dev_x[i];
-        b->host[i].eo = (b->gauges[i]->lat.even_odd_ok() && tuning().eo != 0) ? 1 : 0;
+        b->host[i].eo = (b->gauges[i]->lat.even_odd_ok() && tuning().eo != 0 &&
+                         !b->gauges[i]->C64) ? 1 : 0;
     }
     // the batch stream runs after the caller's stream, and the caller's after it
     StreamJoin join((hipStream_t)stream, b->stream);

@@ -3,7 +3,9 @@
 // (D psi)(x) = (4 + m0) psi(x) - 1/2 sum_mu [ (1 - gamma_mu) U_mu(x) psi(x+mu)
 //                                          + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu) ]
 // (the 12x12-block nearest-neighbour operator of Sec. 1 in Wilson form), and
-// D^dag = gamma5 D gamma5, which swaps the two projectors.
+// D^dag = gamma5 D gamma5, which swaps the two projectors.  A gauge with a
+// clover term adds C(x) psi(x) (C Hermitian and gamma5-even, so the same
+// term serves D and D^dag).
 //
 // Work decomposition: one thread per (site, right-hand side).  The RHS index
 // is innermost in memory, so the lanes of a wavefront read contiguous runs of
@@ -29,8 +31,9 @@
 
 namespace wdt {
 
-template <class S, int NC, bool DAG, int EPI, bool WPS = false>
+template <class S, int NC, bool DAG, int EPI, bool WPS = false, bool CLOV = false>
 __global__ __launch_bounds__(256) void k_dslash(Geom g, const typename S::link *__restrict__ U,
+                                                const typename S::real *__restrict__ Cl,
                                                 SpinorPtr<S> self, typename S::real cs,
                                                 typename S::real ch, SpinorPtr<S> in,
                                                 SpinorPtr<S> out, SpinorPtr<S> aux, int N, int NT,
@@ -40,7 +43,7 @@ __global__ __launch_bounds__(256) void k_dslash(Geom g, const typename S::link *
     if (live && *live == 0) return;
     const int t0 = serial_tiles > 0 ? 0 : (int)blockIdx.y;
     const int t1 = serial_tiles > 0 ? serial_tiles : t0 + 1;
-    dslash_body<S, NC, DAG, EPI, WPS>(g, U, self, cs, ch, in, out, aux, N, NT, SB, partials, t0,
+    dslash_body<S, NC, DAG, EPI, WPS, CLOV>(g, U, Cl, self, cs, ch, in, out, aux, N, NT, SB, partials, t0,
                                       t1, xcd_block(blockIdx.x, gridDim.x), gridDim.x);
 }
 
@@ -71,25 +74,44 @@ struct HopPtrs {
     SpinorPtr<S> self, in, out, aux;
     typename S::real cs, ch;
     const int *live;
+    const typename S::real *clov;  // the clover term or null
 };
 
 template <class S, int NC, bool DAG, int EPI>
 static void launch_k(dim3 grid, int threads, hipStream_t stream, const Geom &g,
                      const typename S::link *U, const HopPtrs<S> &h, int N, int NT, int SB,
                      double2 *part, int serial_tiles, int tc, int4 brick, bool wps) {
+    // the clover operator: its own instantiation (whole lattice, no t-march;
+    // D^dag only without an epilogue, which launch_t checks)
+    if constexpr (!DAG || EPI == EPI_NONE) {
+        if (h.clov) {
+            if constexpr (NC == 48 || NC == 64) {
+                if (wps) {
+                    hipLaunchKernelGGL((k_dslash<S, NC, DAG, EPI, true, true>), grid,
+                                       dim3(threads), 0, stream, g, U, h.clov, h.self, h.cs, h.ch,
+                                       h.in, h.out, h.aux, N, NT, SB, part, serial_tiles, h.live);
+                    return;
+                }
+            }
+            hipLaunchKernelGGL((k_dslash<S, NC, DAG, EPI, false, true>), grid, dim3(threads), 0,
+                               stream, g, U, h.clov, h.self, h.cs, h.ch, h.in, h.out, h.aux, N,
+                               NT, SB, part, serial_tiles, h.live);
+            return;
+        }
+    }
     // the t-march covers the whole lattice with the operator's own form
     const bool march = tc > 0 && g.parity < 0 && h.self.p == h.in.p && h.ch == (typename S::real)(-0.5);
     if constexpr (NC == 48 || NC == 64) {
         if (wps && !march) {
             hipLaunchKernelGGL((k_dslash<S, NC, DAG, EPI, true>), grid, dim3(threads), 0, stream,
-                               g, U, h.self, h.cs, h.ch, h.in, h.out, h.aux, N, NT, SB, part,
-                               serial_tiles, h.live);
+                               g, U, h.clov, h.self, h.cs, h.ch, h.in, h.out, h.aux, N, NT, SB,
+                               part, serial_tiles, h.live);
             return;
         }
         if (wps && march) {
             hipLaunchKernelGGL((k_dslash_march<S, NC, DAG, EPI, true>), grid, dim3(threads), 0,
-                               stream, g, U, h.cs, h.in, h.out, h.aux, N, NT, SB, tc, brick, part,
-                               h.live);
+                               stream, g, U, h.cs, h.in, h.out, h.aux, N, NT, SB, tc, brick,
+                               part, h.live);
             return;
         }
     }
@@ -98,7 +120,7 @@ static void launch_k(dim3 grid, int threads, hipStream_t stream, const Geom &g,
                            U, h.cs, h.in, h.out, h.aux, N, NT, SB, tc, brick, part, h.live);
     else
         hipLaunchKernelGGL((k_dslash<S, NC, DAG, EPI>), grid, dim3(threads), 0, stream, g, U,
-                           h.self, h.cs, h.ch, h.in, h.out, h.aux, N, NT, SB, part, serial_tiles,
+                           h.clov, h.self, h.cs, h.ch, h.in, h.out, h.aux, N, NT, SB, part, serial_tiles,
                            h.live);
 }
 
@@ -142,6 +164,13 @@ static int launch_t(const wdt_gauge_s *gf, const HopSpec &hs, const void *in, vo
     h.cs = (typename S::real)hs.cs;
     h.ch = (typename S::real)hs.ch;
     h.live = hs.live;
+    h.clov = nullptr;
+    if (hs.clover) {
+        if (DAG && EPI != EPI_NONE)
+            return set_error(WDT_EINVAL, "clover operator: D^dag with an epilogue is not built");
+        if constexpr (std::is_same<typename S::real, double>::value) h.clov = gf->C64;
+        else h.clov = gf->C32;
+    }
     const int prec = prec_of<S>();
     // timing classes: the whole-lattice operator, one-parity pure hops, and
     // one-parity launches with the site's own term (the even-odd operator's
@@ -154,8 +183,11 @@ static int launch_t(const wdt_gauge_s *gf, const HopSpec &hs, const void *in, vo
     // algorithmic bytes: in, out, a separate self, the epilogue's vector, links once
     const int nvec = 2 + ((hs.cs != 0.0 && hs.self && hs.self != in) ? 1 : 0) +
                      ((EPI == EPI_DOT_AUX || EPI == EPI_RESID || EPI == EPI_DOT_TSR) ? 1 : 0);
+    const double clov_bytes =
+        h.clov ? (double)V * CLOVER_REALS * sizeof(typename S::real) : 0.0;
     ProfScope prof(names[kind][prec],
-                   (double)g.nsites * N * nvec * site_bytes(prec) + 4.0 * V * link_bytes(prec),
+                   (double)g.nsites * N * nvec * site_bytes(prec) + 4.0 * V * link_bytes(prec) +
+                       clov_bytes,
                    stream);
     switch (nc_of(N)) {
         case 16:
@@ -205,6 +237,8 @@ int launch_hop(const wdt_gauge_s *g, int prec, int dagger, int epi, const HopSpe
                const Shape &sh, hipStream_t stream) {
     if (hs.parity >= 0 && !g->lat.even_odd_ok())
         return set_error(WDT_EINVAL, "one-parity operator on a lattice with an odd extent");
+    if (hs.clover && (hs.parity >= 0 || hs.cs == 0.0 || !g->C64))
+        return set_error(WDT_EINVAL, "clover term: whole-lattice operator with a clover gauge only");
     switch (prec) {
         case WDT_FP64:
             return launch_p<F64>(g, hs, dagger, epi, in, out, aux, N, partials, sh, stream, g->U64);
@@ -227,6 +261,7 @@ int launch_dslash(const wdt_gauge_s *g, double m0, int prec, int dagger, int epi
     hs.self = in;
     hs.cs = 4.0 + m0;
     hs.ch = -0.5;
+    hs.clover = g->C64 != nullptr;
     return launch_hop(g, prec, dagger, epi, hs, in, out, aux, N, partials, sh, stream);
 }
 

@@ -429,6 +429,8 @@ int wdt_force(wdt_gauge g, const void *dev_x, const void *dev_y, int32_t n_rhs,
               const double *grad_out, void *dev_grad_U, double *grad_m0, void *stream) {
     WDT_CHECK(g && dev_x && dev_y && grad_out && dev_grad_U && grad_m0 && n_rhs >= 1,
               "wdt_force: bad argument");
+    WDT_CHECK(g->C64 == nullptr,
+              "wdt_force: the derivative of the clover term is not implemented");
     const hipStream_t st = (hipStream_t)stream;
     const Geom geo = g->lat.geom();
     AsyncScratch scratch(st);

@@ -53,6 +53,11 @@ struct wdt_gauge_s {
     // FP16 operator links: per element u = (ur, ui) the pair (ur, -ui), (ui, ur)
     // of packed halves, so that both parts of u h are single half dot products
     __half2 *U16 = nullptr;
+    // clover term (null without one): per site the two chiral 6 x 6 Hermitian
+    // blocks, packed as 36 reals each (CLOVER_REALS per site); FP64 and FP32
+    double *C64 = nullptr;
+    float *C32 = nullptr;
+    double csw = 0.0;
     Workspace ws;
     // two host-mapped ints (host and device address) for the solvers' loop flag
     int *live_host = nullptr;
@@ -188,15 +193,20 @@ int launch_dslash(const wdt_gauge_s *g, double m0, int prec, int dagger, int epi
 // The general form out = cs * self + ch * H in (H the hop sum of D: D = (4 + m0)
 // - H / 2) on the sites of one parity (parity 0 or 1; lattices with every
 // extent even) or on all sites (parity -1).  self = nullptr means in.
+// clover: out += C self, C the gauge's clover term (all sites, cs != 0 only).
 struct HopSpec {
     int parity = -1;
     const void *self = nullptr;
     double cs = 0.0, ch = 1.0;
+    bool clover = false;
     // solver iterations: the launch does nothing when *live == 0 (device flag)
     const int *live = nullptr;
 };
 int launch_hop(const wdt_gauge_s *g, int prec, int dagger, int epi, const HopSpec &hs,
                const void *in, void *out, const void *aux, int N, double2 *partials,
                const Shape &sh, hipStream_t stream);
+
+// Reals per site of the packed clover term: two chiral blocks of 36.
+constexpr int CLOVER_REALS = 72;
 
 }  // namespace wdt

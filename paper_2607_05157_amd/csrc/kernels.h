@@ -692,6 +692,38 @@ __device__ __forceinline__ void epi_reduce(double2 (&red)[3][256], int tid, int 
     }
 }
 
+// acc += k C c for one site: C the packed clover term, block-diagonal in
+// the two chiralities (spins 0-1 and 2-3, since it commutes with gamma5).
+// Each 6 x 6 Hermitian block is 36 reals: its real diagonal, then the 15
+// elements above it row by row as (re, im).  With k = 1/ch the output
+// cs c + ch acc gains C c.
+template <class R>
+__device__ __forceinline__ void clover_add(const R *__restrict__ C, const cplx<R> (&c)[12], R k,
+                                           cplx<R> (&acc)[12]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const R *A = C + 36 * h;
+        cplx<R> y[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) y[i] = cscale(c[6 * h + i], A[i]);
+        int q = 6;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+#pragma unroll
+            for (int j = i + 1; j < 6; ++j, q += 2) {
+                const cplx<R> a = {A[q], A[q + 1]};
+                y[i] = cfma(y[i], a, c[6 * h + j]);
+                y[j] = cfmaconj(y[j], a, c[6 * h + i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            acc[6 * h + i].re += k * y[i].re;
+            acc[6 * h + i].im += k * y[i].im;
+        }
+    }
+}
+
 // Output of one site, out = cs * c + ch * acc (c: the site's spinor of the
 // self vector, acc: the hop sum), with the epilogue's dot contributions;
 // stores the result.  The operator itself is cs = 4 + m0, ch = -1/2.
@@ -761,9 +793,12 @@ __device__ __forceinline__ void finish_site(typename S::real cs, typename S::rea
 //
 // General form: out(s) = cs * self(s) + ch * H(in)(s), H the hop sum, over
 // the sites of g (one parity when g.parity >= 0); the operator D is
-// self = in, cs = 4 + m0, ch = -1/2.  cs = 0 skips the self load.
-template <class S, int NC, bool DAG, int EPI, bool WPS = false>
+// self = in, cs = 4 + m0, ch = -1/2.  cs = 0 skips the self load.  CLOV
+// (compile-time, so that the plain operator's registers are unaffected; needs
+// cs != 0): the clover term Cl, out(s) += C(s) self(s).
+template <class S, int NC, bool DAG, int EPI, bool WPS = false, bool CLOV = false>
 __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::link *__restrict__ U,
+                                            const typename S::real *__restrict__ Cl,
                                             SpinorPtr<S> self, typename S::real cs,
                                             typename S::real ch, SpinorPtr<S> in,
                                             SpinorPtr<S> out, SpinorPtr<S> aux, int N, int NT,
@@ -800,6 +835,7 @@ __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::lin
             cplx<R> c[12];
             if (cs != R(0)) {
                 load_site<S, NC>(self, s, r, c);
+                if constexpr (CLOV) clover_add<R>(Cl + (size_t)s * CLOVER_REALS, c, R(1) / ch, acc);
             } else {
 #pragma unroll
                 for (int k = 0; k < 12; ++k) c[k] = {R(0), R(0)};

@@ -403,11 +403,12 @@ int bind_live(Bicg &B, int *dev_flag) {
     return WDT_OK;
 }
 
-// Even-odd preconditioning: on when every extent is even, unless the tuner
-// switches it off.
-bool use_even_odd(const wdt_lattice_s &lat) {
+// Even-odd preconditioning: on when every extent is even and the gauge has
+// no clover term (whose odd-site blocks the Schur form would have to invert),
+// unless the tuner switches it off.
+bool use_even_odd(const wdt_gauge_s *g) {
     const int eo = tuning().eo;
-    return lat.even_odd_ok() && eo != 0;
+    return g->lat.even_odd_ok() && eo != 0 && !g->C64;
 }
 
 // The geometry of the sites of one parity, in plain order.
@@ -435,6 +436,7 @@ int apply_op(Bicg &B, int prec, int epi, const void *in, void *out, const void *
         h.cs = a;
         h.ch = -0.5;
         h.live = B.live;
+        h.clover = B.g->C64 != nullptr;
         return launch_hop(B.g, prec, 0, epi, h, in, out, aux, B.N, B.part, B.sh, B.stream);
     }
     HopSpec h1;
@@ -581,7 +583,7 @@ static int solve_fp64(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
     double *bbv = (double *)(base + bb_off);
     Bicg B{g, m0, N, V, sh, geo, NT, dim3(sh.Gv, sh.tiles), stream,
            (RhsState *)(base + st_off), (double2 *)(base + part_off)};
-    B.eo = use_even_odd(g->lat);
+    B.eo = use_even_odd(g);
     if (B.eo) B.geo = parity_geom(g->lat, 0);
     WDT_TRY(bind_live(B, (int *)(base + live_off)));
     WDT_HIP(hipMemsetAsync(B.st, 0, sizeof(RhsState) * N, stream));
@@ -684,7 +686,7 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
     std::vector<double> hfac(3 * nrow, 0.0);
     Bicg B{g, m0, N, V, sh, geo, NT, dim3(sh.Gv, sh.tiles), stream,
            (RhsState *)(base + st_off), (double2 *)(base + part_off)};
-    B.eo = use_even_odd(g->lat);
+    B.eo = use_even_odd(g);
     if (B.eo) B.geo = parity_geom(g->lat, 0);
     WDT_TRY(bind_live(B, (int *)(base + live_off)));
     const dim3 grid(sh.Gv, sh.tiles);

@@ -76,6 +76,8 @@ def lib():
             "wdt_gauge_create": (ctypes.c_int, [vp, P(dbl), P(vp)]),
             "wdt_gauge_destroy": (ctypes.c_int, [vp]),
             "wdt_gauge_get": (ctypes.c_int, [vp, P(dbl)]),
+            "wdt_gauge_set_clover": (ctypes.c_int, [vp, dbl]),
+            "wdt_gauge_get_clover": (ctypes.c_int, [vp, P(dbl)]),
             "wdt_colouring_search": (ctypes.c_int, [P(i32), i32, i32, i32, P(i32), P(i32)]),
             "wdt_colouring_check": (ctypes.c_int, [P(i32), i32, i32, i32, P(i32)]),
             "wdt_sources": (ctypes.c_int, [vp, P(SourceDesc), i32, vp, i32, vp]),
@@ -193,6 +195,19 @@ class Gauge:
         out = np.empty((self.lat.V, 4, 3, 3), dtype=np.complex128)
         check(lib().wdt_gauge_get(self.h, out.view(np.float64).ctypes.data_as(
             ctypes.POINTER(ctypes.c_double))), "wdt_gauge_get")
+        return out
+
+    def set_clover(self, csw):
+        """Adds the clover term with coefficient csw to every later operator
+        application on this gauge (csw = 0 removes it)."""
+        check(lib().wdt_gauge_set_clover(self.h, float(csw)), "wdt_gauge_set_clover")
+
+    def clover_packed(self):
+        """The clover term as stored: [V, 2, 36] (per chiral block its real
+        diagonal, then the elements above it row by row as re, im)."""
+        out = np.empty((self.lat.V, 2, 36), dtype=np.float64)
+        check(lib().wdt_gauge_get_clover(self.h, out.ctypes.data_as(
+            ctypes.POINTER(ctypes.c_double))), "wdt_gauge_get_clover")
         return out
 
     def __del__(self):

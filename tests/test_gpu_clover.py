@@ -1,0 +1,244 @@
+"""GPU parity of the clover-improved operator against the oracle, through the
+C interface: the packed clover blocks, the operator in every storage
+precision (both kernel shapes, D and D^dag), solves against dense LU, the
+batched solver, the estimator's samples, and a full-size solve checked by the
+oracle's residual at sampled sites.  Bars as for the plain operator: FP64
+operator 1e-14 relative, FP32 2e-6, FP16 4e-3, BF16 2^-8 against the
+BF16-rounded input; FP64 solves 1e-10, mixed solves 1e-8 after refinement to
+1e-10."""
+import numpy as np
+import pytest
+
+from oracle import clover, dirac, gamma, noise, solve as osolve
+from synth.gauge import gauge_field
+from test_gpu_parity import bf16_batch, fp16_batch, from_bf16_words, from_fp16, rand_batch, to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+W = None
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    global W
+    from paper_2607_05157_amd import wdt
+    W = wdt
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    wdt.init(0)
+    yield
+
+
+def unpack(P):
+    """[V, 2, 36] packed -> [V, 12, 12] (zero between the chiral blocks)."""
+    V = P.shape[0]
+    C = np.zeros((V, 12, 12), dtype=complex)
+    iu = np.triu_indices(6, 1)
+    for h in range(2):
+        B = np.zeros((V, 6, 6), dtype=complex)
+        B[:, np.arange(6), np.arange(6)] = P[:, h, :6]
+        B[:, iu[0], iu[1]] = P[:, h, 6::2] + 1j * P[:, h, 7::2]
+        B[:, iu[1], iu[0]] = P[:, h, 6::2] - 1j * P[:, h, 7::2]
+        C[:, 6 * h:6 * h + 6, 6 * h:6 * h + 6] = B
+    return C
+
+
+def clover_ref(U, m0, psi, dims, csw, dagger=False):
+    return dirac.apply_D(U, m0, psi, dims, -1, dagger=dagger) + clover.apply_clover(U, dims, csw, psi)
+
+
+@pytest.mark.parametrize("dims,eps,csw", [((4, 4, 2, 6), 0.5, 1.7), ((3, 2, 5, 4), 0.8, -0.9),
+                                          ((2, 2, 2, 2), 0.0, 1.0)])
+def test_clover_blocks_match_oracle(dims, eps, csw):
+    say("clover blocks", dims, eps, csw)
+    U = gauge_field(dims, eps, seed=31)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    g.set_clover(csw)
+    got = unpack(g.clover_packed())
+    ref = clover.clover_blocks(U, dims, csw)
+    scale = max(np.max(np.abs(ref)), 1.0)
+    # the oracle's blocks vanish between the chiralities; the packed form has
+    # the diagonal's real part only (the oracle's imaginary part is rounding)
+    assert np.max(np.abs(got - ref)) < 1e-14 * scale
+    if eps == 0.0:
+        assert np.max(np.abs(got)) == 0
+
+
+@pytest.mark.parametrize("dims,N,dagger", [((4, 4, 2, 6), 1, False), ((4, 4, 2, 6), 48, False),
+                                           ((4, 4, 2, 6), 48, True), ((3, 2, 5, 4), 70, False),
+                                           ((3, 2, 5, 4), 64, True)])
+def test_clover_operator_fp64(dims, N, dagger):
+    say("clover apply_D fp64", dims, N, dagger)
+    V = int(np.prod(dims))
+    U = gauge_field(dims, 0.6, seed=32)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    g.set_clover(1.3)
+    psi = rand_batch(V, N, 3)
+    out = lat.new_batch(N)
+    W.apply_D(g, 0.1, to_dev(psi), out, N, W.FP64, dagger)
+    torch.cuda.synchronize()
+    ref = clover_ref(U, 0.1, psi, dims, 1.3, dagger)
+    err = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    assert err < 1e-14, err
+
+
+@pytest.mark.parametrize("N", [20, 48])
+def test_clover_operator_low_precision(N):
+    dims = (4, 4, 2, 6)
+    say("clover apply_D low precision", N)
+    V = int(np.prod(dims))
+    U = gauge_field(dims, 0.5, seed=33)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    g.set_clover(1.1)
+    psi = rand_batch(V, N, 4)
+    ref = clover_ref(U, 0.05, psi, dims, 1.1)
+    x = torch.from_numpy(np.ascontiguousarray(psi.astype(np.complex64))).cuda()
+    out = torch.zeros_like(x)
+    W.apply_D(g, 0.05, x, out, N, W.FP32)
+    err = np.max(np.abs(out.cpu().numpy().astype(np.complex128) - ref)) / np.max(np.abs(ref))
+    assert err < 2e-6, ("fp32", err)
+    x = fp16_batch(psi)
+    out = torch.zeros_like(x)
+    W.apply_D(g, 0.05, x, out, N, W.FP16)
+    err = np.max(np.abs(from_fp16(out, V, N) - ref)) / np.max(np.abs(ref))
+    assert err < 4e-3, ("fp16", err)
+    x, psi_r = bf16_batch(psi)
+    psi_r = psi_r.reshape(V, 12, N)
+    for dagger in (False, True):
+        ref = clover_ref(U, 0.05, psi_r, dims, 1.1, dagger)
+        out = torch.zeros_like(x)
+        W.apply_D(g, 0.05, x, out, N, W.BF16, dagger)
+        res = from_bf16_words(out.cpu().numpy().view(np.uint32)).reshape(V, 12, N)
+        err = np.max(np.abs(res - ref) / (np.abs(ref) + 1e-3 * np.max(np.abs(ref))))
+        assert err < 2 ** -8, ("bf16", dagger, err)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    dims, m0, csw = (4, 4, 2, 4), 0.05, 1.4
+    U = gauge_field(dims, 0.4, seed=34)
+    Dinv = osolve.dense_inverse(clover.dense_D_clover(U, m0, dims, csw))
+    return dims, m0, csw, U, Dinv
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16", "bf16"])
+def test_clover_solve_and_samples_match_dense_lu(c2, prec):
+    """Solutions, Hutchinson samples and the gamma5 loop at t = 0 against the
+    dense inverse of the clover operator (every extent even: the solver must
+    still use the whole-lattice operator)."""
+    dims, m0, csw, U, Dinv = c2
+    say("clover solve", prec)
+    V, N = int(np.prod(dims)), 24
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    g.set_clover(csw)
+    b = lat.new_batch(N)
+    W.sources(lat, W.source_descs(list(range(N))), b)
+    x = lat.new_batch(N)
+    p = {"fp64": W.FP64, "fp16": W.FP16, "bf16": W.BF16}[prec]
+    tol, bar = (1e-12, 1e-10) if prec == "fp64" else (1e-10, 1e-8)
+    kw = {"inner_tol": 0.05} if prec == "bf16" else {}
+    rc, st = W.solve(g, m0, b, x, N, tol=tol, prec=p, **kw)
+    assert rc == W.OK and all(s["converged"] for s in st)
+    E = np.stack([noise.rademacher(s, 12 * V) for s in range(N)], axis=1).astype(complex)
+    assert np.array_equal(b.cpu().numpy().reshape(-1, N), E)
+    X = Dinv @ E
+    xs = x.cpu().numpy().reshape(-1, N)
+    assert np.max(np.linalg.norm(xs - X, axis=0) / np.linalg.norm(X, axis=0)) < bar
+    full = W.contract(lat, b, x, N).sum(axis=1)
+    ref = np.einsum("ik,ik->k", np.conj(E), X)
+    norms = np.linalg.norm(E, axis=0) * np.linalg.norm(X, axis=0)
+    assert np.all(np.abs(full - ref) <= bar * norms)
+
+
+def test_clover_batched_next_to_plain_system(c2):
+    """The batched solver with one clover system (even extents: solved on the
+    whole lattice) beside a plain Wilson system (even-odd)."""
+    dims, m0, csw, U, Dinv = c2
+    say("clover batched")
+    lat = W.Lattice(dims, -1)
+    g1 = W.Gauge(lat, U)
+    g1.set_clover(csw)
+    U2 = gauge_field((4, 4, 4, 4), 0.3, seed=35)
+    lat2 = W.Lattice((4, 4, 4, 4), -1)
+    g2 = W.Gauge(lat2, U2)
+    N1, N2 = 8, 5
+    b1, b2 = lat.new_batch(N1), lat2.new_batch(N2)
+    W.sources(lat, W.source_descs(list(range(N1))), b1)
+    W.sources(lat2, W.source_descs([100 + k for k in range(N2)]), b2)
+    B = W.Batch([g1, g2], [m0, 0.2], [N1, N2])
+    x1, x2 = lat.new_batch(N1), lat2.new_batch(N2)
+    rc, st = B.solve([b1, b2], [x1, x2], tol=1e-11)
+    assert rc == W.OK and all(t["converged"] for t in st)
+    X = Dinv @ b1.cpu().numpy().reshape(-1, N1)
+    xs = x1.cpu().numpy().reshape(-1, N1)
+    assert np.max(np.linalg.norm(xs - X, axis=0) / np.linalg.norm(X, axis=0)) < 1e-9
+    r2 = b2.cpu().numpy() - dirac.apply_D(U2, 0.2, x2.cpu().numpy(), (4, 4, 4, 4), -1)
+    assert np.max(np.linalg.norm(r2.reshape(-1, N2), axis=0)
+                  / np.linalg.norm(b2.cpu().numpy().reshape(-1, N2), axis=0)) <= 1.01e-11
+
+
+def test_clover_removed_and_force_rejected():
+    dims, N = (4, 4, 2, 6), 16
+    say("clover on/off")
+    V = int(np.prod(dims))
+    U = gauge_field(dims, 0.5, seed=36)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    psi = to_dev(rand_batch(V, N, 5))
+    plain = lat.new_batch(N)
+    W.apply_D(g, 0.1, psi, plain, N, W.FP64)
+    with pytest.raises(RuntimeError):
+        g.clover_packed()
+    g.set_clover(1.5)
+    with_c = lat.new_batch(N)
+    W.apply_D(g, 0.1, psi, with_c, N, W.FP64)
+    assert not torch.equal(with_c, plain)
+    gU = torch.zeros((V, 4, 3, 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(RuntimeError):
+        W.force(g, psi, psi, N, np.ones(N, dtype=complex), gU)
+    g.set_clover(0.0)
+    again = lat.new_batch(N)
+    W.apply_D(g, 0.1, psi, again, N, W.FP64)
+    assert torch.equal(again, plain)
+
+
+def test_clover_full_size_solve_sampled_residual():
+    """16^3 x 32, 48 RHS, mixed FP16 solve with the clover term: the oracle's
+    residual b - D_sw x at sampled sites (on the source slice, next to it,
+    anywhere) is within the solve tolerance."""
+    dims, m0, csw, N, t0 = (16, 16, 16, 32), -0.05, 1.0, 48, 5
+    say("clover full size 16^3x32")
+    V = int(np.prod(dims))
+    Lxyz = dims[0] * dims[1] * dims[2]
+    U = gauge_field(dims, 0.3, seed=37)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    g.set_clover(csw)
+    d = W.source_descs(list(range(N)), t0=t0)
+    b = lat.new_batch(N)
+    W.sources(lat, d, b)
+    x = lat.new_batch(N)
+    rc, st = W.solve(g, m0, b, x, N, tol=1e-10, prec=W.FP16)
+    assert rc == W.OK and all(s["converged"] for s in st)
+    rng = np.random.default_rng(38)
+    sites = np.concatenate([t0 * Lxyz + rng.integers(0, Lxyz, 64),
+                            (t0 + 1) * Lxyz + rng.integers(0, Lxyz, 32), rng.integers(0, V, 32)])
+    sites = [int(s) for s in sites]
+    C = clover.clover_blocks(U, dims, csw)
+    xh = x.cpu().numpy()
+    Dx = dirac.apply_D_sites(U, m0, lambda s: xh[s], dims, sites, -1)
+    Dx += np.einsum("sij,sjn->sin", C[sites], xh[sites])
+    bh = b.cpu().numpy()
+    r = bh[sites] - Dx
+    nb = np.linalg.norm(bh.reshape(-1, N), axis=0)
+    rel = np.linalg.norm(r.transpose(2, 0, 1).reshape(N, -1), axis=1) / nb
+    assert np.max(rel) <= 1.01e-10, np.max(rel)

@@ -96,7 +96,7 @@ def _random_su3(n, rng):
 
 def test_gauge_covariance_of_clover_operator():
     """U_mu(x) -> W(x) U_mu(x) W(x + mu)^dag maps the clover blocks to
-    W(x) C(x) W(x)^dag and leaves tr D^-1 and the slice traces unchanged."""
+    W(x) C(x) W(x)^dag and leaves tr D^-1 unchanged."""
     dims, m0, csw = (2, 2, 2, 4), 0.2, 1.1
     U = gauge_field(dims, 0.5, seed=4)
     V = volume(dims)
