@@ -229,7 +229,7 @@ def main():
         t_bf16 = (time.perf_counter() - t0_) / args.bf16_steps
 
     # the same steps with the clover term (c_sw = 1, its tree-level value) on
-    # the operator: no even-odd preconditioning then, for the record
+    # the operator, for the record
     t_clov, clov = None, None
     if args.clover_steps > 0:
         log("clover steps", args.clover_steps, "after one warm-up step")
@@ -252,10 +252,10 @@ def main():
         pc = wdt.profile_read()
         wdt.profile(False)
         del gc
-        op = pc.get("dslash_fp16")
         clov = {"csw": 1.0, "iterations_max": max(its),
-                "dslash_fp16_clover_gbps": round(op["gbps"], 1) if op else None,
-                "dslash_fp16_clover_calls": op["calls"] if op else None}
+                "kernels": {k: {"calls": v["calls"], "ms": round(v["ms"], 3),
+                                "gbps": round(v["gbps"], 1)}
+                            for k, v in pc.items() if k.startswith("dslash")}}
 
     log("fp64 steps", args.fp64_steps)
     torch.cuda.synchronize()

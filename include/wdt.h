@@ -118,9 +118,13 @@ int wdt_gauge_get(wdt_gauge g, double *host_links);
  * wdt_gauge_set_clover builds C from the FP64 links (FP64, plus an FP32 copy
  * for the FP32 / FP16 / BF16 operators: 72 * 12 bytes per site of device
  * memory, allocated on the first call).  csw = 0 frees it.  Synchronous.
- * While a clover term is set, solves run without even-odd preconditioning
- * (the Schur form would need the inverse odd-site blocks) and wdt_force
- * returns WDT_EINVAL (the term's derivative is not implemented).
+ * Even-odd preconditioned solves then use the inverse blocks (4 + m0 + C)^-1
+ * on the odd sites, computed on the solve's stream at the first solve with a
+ * given m0 and kept with the gauge (another 72 * 12 bytes per site); solves
+ * on one gauge with different m0 must therefore not run concurrently.  The
+ * batched solver takes clover systems without even-odd preconditioning.
+ * wdt_force returns WDT_EINVAL while a term is set (its derivative is not
+ * implemented).
  * WDT_EINVAL for a null handle or a non-finite csw.
  *
  * wdt_gauge_get_clover copies C to host_packed (host, V * 72 doubles): per

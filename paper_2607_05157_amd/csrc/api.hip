@@ -278,6 +278,8 @@ int wdt_gauge_destroy(wdt_gauge g) {
     (void)hipFree(g->U16);
     if (g->C64) (void)hipFree(g->C64);
     if (g->C32) (void)hipFree(g->C32);
+    if (g->Ci64) (void)hipFree(g->Ci64);
+    if (g->Ci32) (void)hipFree(g->Ci32);
     if (g->ws.ptr) (void)hipFree(g->ws.ptr);
     if (g->live_host) (void)hipHostFree(g->live_host);
     delete g;

@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void kb_dslash(const SysDesc *sys, int nsys, i
                                                  int aux) {
     WDT_SYS_CTX
     if (d.C)
-        dslash_body<F64, 0, false, EPI, false, true>(d.g, d.U, d.C, sp(in), d.diag, -0.5, sp(in),
+        dslash_body<F64, 0, false, EPI, false, 1>(d.g, d.U, d.C, sp(in), d.diag, -0.5, sp(in),
                                                      sp(out), sp(aux >= 0 ? aux : in), d.N, d.NT,
                                                      d.SB, d.part, tile, tile + 1, lb, d.G);
     else
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void kb_op_even(const SysDesc *sys, int nsys, 
                                         -0.25 / d.diag, sp(out), sp(out), pa, d.N, d.NT, d.SB,
                                         d.part, tile, tile + 1, lb, d.G);
     else if (d.C)
-        dslash_body<F64, 0, false, EPI, false, true>(d.g, d.U, d.C, sp(in), d.diag, -0.5, sp(in),
+        dslash_body<F64, 0, false, EPI, false, 1>(d.g, d.U, d.C, sp(in), d.diag, -0.5, sp(in),
                                                      sp(out), pa, d.N, d.NT, d.SB, d.part, tile,
                                                      tile + 1, lb, d.G);
     else

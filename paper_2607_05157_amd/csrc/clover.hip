@@ -164,6 +164,106 @@ __global__ __launch_bounds__(128) void k_clover_build(const double2 *__restrict_
     }
 }
 
+// (a + C)^-1 per site and chirality, one thread each: the packed 6 x 6 block
+// plus a on the diagonal, inverted by Gauss-Jordan elimination with partial
+// pivoting in FP64, written back in the packed form (the inverse of a
+// Hermitian matrix is Hermitian: its diagonal's real part and the elements
+// above it are kept); FP32 copy rounded from it.
+__global__ __launch_bounds__(128) void k_clover_inverse(const double *__restrict__ C, double a,
+                                                        int nblk, double *__restrict__ Ci64,
+                                                        float *__restrict__ Ci32) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nblk) return;
+    const double *A = C + (size_t)t * 36;
+    double2 M[6][12];
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 12; ++j) M[i][j] = make_double2(0.0, 0.0);
+    for (int i = 0; i < 6; ++i) {
+        M[i][i] = make_double2(a + A[i], 0.0);
+        M[i][6 + i] = make_double2(1.0, 0.0);
+    }
+    int q = 6;
+    for (int i = 0; i < 6; ++i)
+        for (int j = i + 1; j < 6; ++j, q += 2) {
+            M[i][j] = make_double2(A[q], A[q + 1]);
+            M[j][i] = make_double2(A[q], -A[q + 1]);
+        }
+    for (int col = 0; col < 6; ++col) {
+        int piv = col;
+        double best = M[col][col].x * M[col][col].x + M[col][col].y * M[col][col].y;
+        for (int i = col + 1; i < 6; ++i) {
+            const double m = M[i][col].x * M[i][col].x + M[i][col].y * M[i][col].y;
+            if (m > best) {
+                best = m;
+                piv = i;
+            }
+        }
+        if (piv != col)
+            for (int j = 0; j < 12; ++j) {
+                const double2 tmp = M[col][j];
+                M[col][j] = M[piv][j];
+                M[piv][j] = tmp;
+            }
+        // row col /= pivot
+        const double2 p = M[col][col];
+        const double inv = 1.0 / (p.x * p.x + p.y * p.y);
+        const double2 rp = make_double2(p.x * inv, -p.y * inv);
+        for (int j = 0; j < 12; ++j) {
+            const double2 v = M[col][j];
+            M[col][j] = make_double2(v.x * rp.x - v.y * rp.y, v.x * rp.y + v.y * rp.x);
+        }
+        for (int i = 0; i < 6; ++i) {
+            if (i == col) continue;
+            const double2 f = M[i][col];
+            for (int j = 0; j < 12; ++j) {
+                const double2 v = M[col][j];
+                M[i][j].x -= f.x * v.x - f.y * v.y;
+                M[i][j].y -= f.x * v.y + f.y * v.x;
+            }
+        }
+    }
+    double *o64 = Ci64 + (size_t)t * 36;
+    float *o32 = Ci32 + (size_t)t * 36;
+    for (int i = 0; i < 6; ++i) {
+        o64[i] = M[i][6 + i].x;
+        o32[i] = (float)M[i][6 + i].x;
+    }
+    q = 6;
+    for (int i = 0; i < 6; ++i)
+        for (int j = i + 1; j < 6; ++j, q += 2) {
+            o64[q] = M[i][6 + j].x;
+            o64[q + 1] = M[i][6 + j].y;
+            o32[q] = (float)M[i][6 + j].x;
+            o32[q + 1] = (float)M[i][6 + j].y;
+        }
+}
+
+int ensure_clover_inverse(wdt_gauge_s *g, double a, hipStream_t stream) {
+    if (!g->C64) return set_error(WDT_EINVAL, "clover inverse blocks without a clover term");
+    if (g->Ci64 && g->ci_a == a) return WDT_OK;
+    const size_t n = (size_t)g->lat.V * CLOVER_REALS;
+    if (!g->Ci64) {
+        double *c64 = nullptr;
+        float *c32 = nullptr;
+        const hipError_t e1 = hipMalloc(&c64, n * sizeof(double));
+        const hipError_t e2 = e1 == hipSuccess ? hipMalloc(&c32, n * sizeof(float)) : e1;
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            (void)hipGetLastError();
+            if (c64) (void)hipFree(c64);
+            return set_error(WDT_ENOMEM, "clover inverse blocks: device allocation failed");
+        }
+        g->Ci64 = c64;
+        g->Ci32 = c32;
+    }
+    const int nblk = (int)(g->lat.V * 2);
+    const int threads = 128;
+    hipLaunchKernelGGL(k_clover_inverse, dim3((nblk + threads - 1) / threads), dim3(threads), 0,
+                       stream, g->C64, a, nblk, g->Ci64, g->Ci32);
+    WDT_HIP(hipGetLastError());
+    g->ci_a = a;
+    return WDT_OK;
+}
+
 // The DeGrand-Rossi gamma matrices (mu = x, y, z, t), in which gamma5 =
 // diag(1, 1, -1, -1); the operator kernels' spin projectors use the same basis.
 static void gamma_dr(int mu, double2 (&m)[4][4]) {
@@ -232,11 +332,17 @@ extern "C" int wdt_gauge_set_clover(wdt_gauge g, double csw) {
     using namespace wdt;
     WDT_CHECK(g != nullptr, "wdt_gauge_set_clover: null gauge handle");
     WDT_CHECK(std::isfinite(csw), "wdt_gauge_set_clover: c_sw must be finite");
+    // the inverse blocks belong to the old term
+    g->ci_a = std::nan("");
     if (csw == 0.0) {
         if (g->C64) (void)hipFree(g->C64);
         if (g->C32) (void)hipFree(g->C32);
+        if (g->Ci64) (void)hipFree(g->Ci64);
+        if (g->Ci32) (void)hipFree(g->Ci32);
         g->C64 = nullptr;
         g->C32 = nullptr;
+        g->Ci64 = nullptr;
+        g->Ci32 = nullptr;
         g->csw = 0.0;
         return WDT_OK;
     }

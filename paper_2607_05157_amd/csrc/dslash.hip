@@ -31,7 +31,7 @@
 
 namespace wdt {
 
-template <class S, int NC, bool DAG, int EPI, bool WPS = false, bool CLOV = false>
+template <class S, int NC, bool DAG, int EPI, bool WPS = false, int CLOV = 0>
 __global__ __launch_bounds__(256) void k_dslash(Geom g, const typename S::link *__restrict__ U,
                                                 const typename S::real *__restrict__ Cl,
                                                 SpinorPtr<S> self, typename S::real cs,
@@ -74,26 +74,44 @@ struct HopPtrs {
     SpinorPtr<S> self, in, out, aux;
     typename S::real cs, ch;
     const int *live;
-    const typename S::real *clov;  // the clover term or null
+    const typename S::real *clov;  // the clover term, its inverse blocks, or null
+    int cmode;                     // 1: add the clover term; 2: multiply by the inverse blocks
 };
 
 template <class S, int NC, bool DAG, int EPI>
 static void launch_k(dim3 grid, int threads, hipStream_t stream, const Geom &g,
                      const typename S::link *U, const HopPtrs<S> &h, int N, int NT, int SB,
                      double2 *part, int serial_tiles, int tc, int4 brick, bool wps) {
-    // the clover operator: its own instantiation (whole lattice, no t-march;
-    // D^dag only without an epilogue, which launch_t checks)
+    // the clover operator and the inverse-block launches: their own
+    // instantiations (no t-march; D^dag only without an epilogue, the inverse
+    // blocks only for D without one, which launch_t checks)
     if constexpr (!DAG || EPI == EPI_NONE) {
-        if (h.clov) {
+        if (h.clov && h.cmode == 1) {
             if constexpr (NC == 48 || NC == 64) {
                 if (wps) {
-                    hipLaunchKernelGGL((k_dslash<S, NC, DAG, EPI, true, true>), grid,
+                    hipLaunchKernelGGL((k_dslash<S, NC, DAG, EPI, true, 1>), grid,
                                        dim3(threads), 0, stream, g, U, h.clov, h.self, h.cs, h.ch,
                                        h.in, h.out, h.aux, N, NT, SB, part, serial_tiles, h.live);
                     return;
                 }
             }
-            hipLaunchKernelGGL((k_dslash<S, NC, DAG, EPI, false, true>), grid, dim3(threads), 0,
+            hipLaunchKernelGGL((k_dslash<S, NC, DAG, EPI, false, 1>), grid, dim3(threads), 0,
+                               stream, g, U, h.clov, h.self, h.cs, h.ch, h.in, h.out, h.aux, N,
+                               NT, SB, part, serial_tiles, h.live);
+            return;
+        }
+    }
+    if constexpr (!DAG && EPI == EPI_NONE) {
+        if (h.clov && h.cmode == 2) {
+            if constexpr (NC == 48 || NC == 64) {
+                if (wps) {
+                    hipLaunchKernelGGL((k_dslash<S, NC, DAG, EPI, true, 2>), grid,
+                                       dim3(threads), 0, stream, g, U, h.clov, h.self, h.cs, h.ch,
+                                       h.in, h.out, h.aux, N, NT, SB, part, serial_tiles, h.live);
+                    return;
+                }
+            }
+            hipLaunchKernelGGL((k_dslash<S, NC, DAG, EPI, false, 2>), grid, dim3(threads), 0,
                                stream, g, U, h.clov, h.self, h.cs, h.ch, h.in, h.out, h.aux, N,
                                NT, SB, part, serial_tiles, h.live);
             return;
@@ -165,11 +183,19 @@ static int launch_t(const wdt_gauge_s *gf, const HopSpec &hs, const void *in, vo
     h.ch = (typename S::real)hs.ch;
     h.live = hs.live;
     h.clov = nullptr;
+    h.cmode = 0;
     if (hs.clover) {
         if (DAG && EPI != EPI_NONE)
             return set_error(WDT_EINVAL, "clover operator: D^dag with an epilogue is not built");
         if constexpr (std::is_same<typename S::real, double>::value) h.clov = gf->C64;
         else h.clov = gf->C32;
+        h.cmode = 1;
+    } else if (hs.clover_inv) {
+        if (DAG || EPI != EPI_NONE)
+            return set_error(WDT_EINVAL, "clover inverse blocks: D without an epilogue only");
+        if constexpr (std::is_same<typename S::real, double>::value) h.clov = gf->Ci64;
+        else h.clov = gf->Ci32;
+        h.cmode = 2;
     }
     const int prec = prec_of<S>();
     // timing classes: the whole-lattice operator, one-parity pure hops, and
@@ -184,7 +210,7 @@ static int launch_t(const wdt_gauge_s *gf, const HopSpec &hs, const void *in, vo
     const int nvec = 2 + ((hs.cs != 0.0 && hs.self && hs.self != in) ? 1 : 0) +
                      ((EPI == EPI_DOT_AUX || EPI == EPI_RESID || EPI == EPI_DOT_TSR) ? 1 : 0);
     const double clov_bytes =
-        h.clov ? (double)V * CLOVER_REALS * sizeof(typename S::real) : 0.0;
+        h.clov ? (double)g.nsites * CLOVER_REALS * sizeof(typename S::real) : 0.0;
     ProfScope prof(names[kind][prec],
                    (double)g.nsites * N * nvec * site_bytes(prec) + 4.0 * V * link_bytes(prec) +
                        clov_bytes,
@@ -237,8 +263,10 @@ int launch_hop(const wdt_gauge_s *g, int prec, int dagger, int epi, const HopSpe
                const Shape &sh, hipStream_t stream) {
     if (hs.parity >= 0 && !g->lat.even_odd_ok())
         return set_error(WDT_EINVAL, "one-parity operator on a lattice with an odd extent");
-    if (hs.clover && (hs.parity >= 0 || hs.cs == 0.0 || !g->C64))
-        return set_error(WDT_EINVAL, "clover term: whole-lattice operator with a clover gauge only");
+    if (hs.clover && (hs.cs == 0.0 || hs.clover_inv || !g->C64))
+        return set_error(WDT_EINVAL, "clover term: needs the site's own term and a clover gauge");
+    if (hs.clover_inv && !g->Ci64)
+        return set_error(WDT_EINVAL, "clover inverse blocks not computed");
     switch (prec) {
         case WDT_FP64:
             return launch_p<F64>(g, hs, dagger, epi, in, out, aux, N, partials, sh, stream, g->U64);

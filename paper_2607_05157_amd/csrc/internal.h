@@ -58,6 +58,11 @@ struct wdt_gauge_s {
     double *C64 = nullptr;
     float *C32 = nullptr;
     double csw = 0.0;
+    // (a + C)^-1 in the same packed form for the even-odd solves, for the
+    // a = 4 + m0 in ci_a (NaN: not computed since the term last changed)
+    double *Ci64 = nullptr;
+    float *Ci32 = nullptr;
+    double ci_a = __builtin_nan("");
     Workspace ws;
     // two host-mapped ints (host and device address) for the solvers' loop flag
     int *live_host = nullptr;
@@ -193,12 +198,15 @@ int launch_dslash(const wdt_gauge_s *g, double m0, int prec, int dagger, int epi
 // The general form out = cs * self + ch * H in (H the hop sum of D: D = (4 + m0)
 // - H / 2) on the sites of one parity (parity 0 or 1; lattices with every
 // extent even) or on all sites (parity -1).  self = nullptr means in.
-// clover: out += C self, C the gauge's clover term (all sites, cs != 0 only).
+// clover: out += C self, C the gauge's clover term (cs != 0 only).
+// clover_inv: out = (a + C)^-1 (cs self + ch H in) instead, with the inverse
+// blocks of ensure_clover_inverse (no epilogue, D only).
 struct HopSpec {
     int parity = -1;
     const void *self = nullptr;
     double cs = 0.0, ch = 1.0;
     bool clover = false;
+    bool clover_inv = false;
     // solver iterations: the launch does nothing when *live == 0 (device flag)
     const int *live = nullptr;
 };
@@ -208,5 +216,9 @@ int launch_hop(const wdt_gauge_s *g, int prec, int dagger, int epi, const HopSpe
 
 // Reals per site of the packed clover term: two chiral blocks of 36.
 constexpr int CLOVER_REALS = 72;
+
+// Makes g->Ci64 / Ci32 hold (a + C(x))^-1 on every site (no-op when they
+// already do for this a).  Stream-ordered on `stream`.
+int ensure_clover_inverse(wdt_gauge_s *g, double a, hipStream_t stream);
 
 }  // namespace wdt

@@ -794,9 +794,11 @@ __device__ __forceinline__ void finish_site(typename S::real cs, typename S::rea
 // General form: out(s) = cs * self(s) + ch * H(in)(s), H the hop sum, over
 // the sites of g (one parity when g.parity >= 0); the operator D is
 // self = in, cs = 4 + m0, ch = -1/2.  cs = 0 skips the self load.  CLOV
-// (compile-time, so that the plain operator's registers are unaffected; needs
-// cs != 0): the clover term Cl, out(s) += C(s) self(s).
-template <class S, int NC, bool DAG, int EPI, bool WPS = false, bool CLOV = false>
+// (compile-time, so that the plain operator's registers are unaffected):
+// 1, the clover term Cl, out(s) += C(s) self(s) (needs cs != 0); 2, Cl holds
+// the inverse blocks (a + C)^-1 and out(s) = Cl(s) (cs self(s) + ch H(in)(s))
+// (EPI_NONE only).
+template <class S, int NC, bool DAG, int EPI, bool WPS = false, int CLOV = 0>
 __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::link *__restrict__ U,
                                             const typename S::real *__restrict__ Cl,
                                             SpinorPtr<S> self, typename S::real cs,
@@ -835,12 +837,25 @@ __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::lin
             cplx<R> c[12];
             if (cs != R(0)) {
                 load_site<S, NC>(self, s, r, c);
-                if constexpr (CLOV) clover_add<R>(Cl + (size_t)s * CLOVER_REALS, c, R(1) / ch, acc);
+                if constexpr (CLOV == 1)
+                    clover_add<R>(Cl + (size_t)s * CLOVER_REALS, c, R(1) / ch, acc);
             } else {
 #pragma unroll
                 for (int k = 0; k < 12; ++k) c[k] = {R(0), R(0)};
             }
-            finish_site<S, NC, EPI>(cs, ch, c, acc, out, aux, s, r, e);
+            if constexpr (CLOV == 2) {
+                static_assert(EPI == EPI_NONE, "inverse blocks: no epilogue");
+                cplx<R> o[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    o[k] = {cs * c[k].re + ch * acc[k].re, cs * c[k].im + ch * acc[k].im};
+                    acc[k] = {R(0), R(0)};
+                }
+                clover_add<R>(Cl + (size_t)s * CLOVER_REALS, o, R(1), acc);
+                finish_site<S, NC, EPI>(R(0), R(1), c, acc, out, aux, s, r, e);
+            } else {
+                finish_site<S, NC, EPI>(cs, ch, c, acc, out, aux, s, r, e);
+            }
         }
     }
     if constexpr (EPI != EPI_NONE) {

@@ -403,12 +403,11 @@ int bind_live(Bicg &B, int *dev_flag) {
     return WDT_OK;
 }
 
-// Even-odd preconditioning: on when every extent is even and the gauge has
-// no clover term (whose odd-site blocks the Schur form would have to invert),
-// unless the tuner switches it off.
+// Even-odd preconditioning: on when every extent is even, unless the tuner
+// switches it off.
 bool use_even_odd(const wdt_gauge_s *g) {
     const int eo = tuning().eo;
-    return g->lat.even_odd_ok() && eo != 0 && !g->C64;
+    return g->lat.even_odd_ok() && eo != 0;
 }
 
 // The geometry of the sites of one parity, in plain order.
@@ -424,6 +423,11 @@ Geom parity_geom(const wdt_lattice_s &lat, int parity) {
 // eliminated:
 //   M x_e = a x_e - (1/(4a)) H_eo H_oe x_e = b_e + (1/(2a)) H_eo b_o =: b'_e,
 //   x_o = (1/a) b_o + (1/(2a)) H_oe x_e.
+// With a clover term the site's own term is the block A = a + C(x) and 1/a
+// becomes A_oo^-1 (inverse blocks on the odd sites, applied in the hop
+// launch that produces the odd-site vector):
+//   M x_e = A_ee x_e - (1/4) H_eo A_oo^-1 H_oe x_e,
+//   x_o = A_oo^-1 (b_o + (1/2) H_oe x_e).
 // The residual of x = (x_e, x_o) is then b'_e - M x_e on the even sites and
 // exactly zero on the odd ones, so the Schur residual is the true residual.
 // Vectors keep the full-lattice layout; the iteration touches even sites only
@@ -439,29 +443,35 @@ int apply_op(Bicg &B, int prec, int epi, const void *in, void *out, const void *
         h.clover = B.g->C64 != nullptr;
         return launch_hop(B.g, prec, 0, epi, h, in, out, aux, B.N, B.part, B.sh, B.stream);
     }
+    const bool clov = B.g->C64 != nullptr;
     HopSpec h1;
     h1.parity = 1;
     h1.cs = 0.0;
     h1.ch = 1.0;
     h1.live = B.live;
+    h1.clover_inv = clov;
     WDT_TRY(launch_hop(B.g, prec, 0, EPI_NONE, h1, in, out, nullptr, B.N, nullptr, B.sh, B.stream));
     HopSpec h2;
     h2.parity = 0;
     h2.self = in;
     h2.cs = a;
-    h2.ch = -1.0 / (4.0 * a);
+    h2.ch = clov ? -0.25 : -1.0 / (4.0 * a);
+    h2.clover = clov;
     h2.live = B.live;
     return launch_hop(B.g, prec, 0, epi, h2, out, out, aux, B.N, B.part, B.sh, B.stream);
 }
 
-// x_o = (1/a) b_o + (1/(2a)) H_oe x_e in place on the odd sites of x.
+// x_o = (1/a) b_o + (1/(2a)) H_oe x_e in place on the odd sites of x
+// (with a clover term x_o = A_oo^-1 (b_o + (1/2) H_oe x_e)).
 int schur_odd(Bicg &B, int prec, const void *b, void *x) {
     const double a = 4.0 + B.m0;
+    const bool clov = B.g->C64 != nullptr;
     HopSpec h;
     h.parity = 1;
     h.self = b;
-    h.cs = 1.0 / a;
-    h.ch = 1.0 / (2.0 * a);
+    h.cs = clov ? 1.0 : 1.0 / a;
+    h.ch = clov ? 0.5 : 1.0 / (2.0 * a);
+    h.clover_inv = clov;
     return launch_hop(B.g, prec, 0, EPI_NONE, h, x, x, nullptr, B.N, nullptr, B.sh, B.stream);
 }
 
@@ -585,6 +595,7 @@ static int solve_fp64(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
            (RhsState *)(base + st_off), (double2 *)(base + part_off)};
     B.eo = use_even_odd(g);
     if (B.eo) B.geo = parity_geom(g->lat, 0);
+    if (B.eo && g->C64) WDT_TRY(ensure_clover_inverse(g, 4.0 + m0, stream));
     WDT_TRY(bind_live(B, (int *)(base + live_off)));
     WDT_HIP(hipMemsetAsync(B.st, 0, sizeof(RhsState) * N, stream));
     if (!P.x0_is_guess) WDT_HIP(hipMemsetAsync(x, 0, vb, stream));
@@ -610,6 +621,7 @@ static int solve_fp64(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
             h.self = x;
             h.cs = 4.0 + m0;
             h.ch = -0.5;
+            h.clover = g->C64 != nullptr;
             WDT_TRY(launch_hop(g, WDT_FP64, 0, EPI_RESID, h, x, r, b, N, B.part, sh, stream));
         } else {
             WDT_TRY(launch_dslash(g, m0, WDT_FP64, 0, EPI_RESID, x, r, b, N, B.part, sh, stream));
@@ -688,6 +700,7 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
            (RhsState *)(base + st_off), (double2 *)(base + part_off)};
     B.eo = use_even_odd(g);
     if (B.eo) B.geo = parity_geom(g->lat, 0);
+    if (B.eo && g->C64) WDT_TRY(ensure_clover_inverse(g, 4.0 + m0, stream));
     WDT_TRY(bind_live(B, (int *)(base + live_off)));
     const dim3 grid(sh.Gv, sh.tiles);
     // the sites the defect correction updates: all, or the even ones
@@ -721,6 +734,7 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
             h.self = x;
             h.cs = a;
             h.ch = -0.5;
+            h.clover = g->C64 != nullptr;
             WDT_TRY(launch_hop(g, WDT_FP64, 0, EPI_RESID, h, x, r64, b, N, B.part, sh, stream));
         } else {
             WDT_TRY(launch_dslash(g, m0, WDT_FP64, 0, EPI_RESID, x, r64, b, N, B.part, sh, stream));

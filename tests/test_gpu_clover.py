@@ -1,6 +1,7 @@
 """GPU parity of the clover-improved operator against the oracle, through the
 C interface: the packed clover blocks, the operator in every storage
-precision (both kernel shapes, D and D^dag), solves against dense LU, the
+precision (both kernel shapes, D and D^dag), solves against dense LU (even-odd
+preconditioned with the inverse odd-site blocks, and not), the
 batched solver, the estimator's samples, and a full-size solve checked by the
 oracle's residual at sampled sites.  Bars as for the plain operator: FP64
 operator 1e-14 relative, FP32 2e-6, FP16 4e-3, BF16 2^-8 against the
@@ -131,32 +132,65 @@ def c2():
 
 @pytest.mark.parametrize("prec", ["fp64", "fp16", "bf16"])
 def test_clover_solve_and_samples_match_dense_lu(c2, prec):
-    """Solutions, Hutchinson samples and the gamma5 loop at t = 0 against the
-    dense inverse of the clover operator (every extent even: the solver must
-    still use the whole-lattice operator)."""
+    """Solutions and Hutchinson samples against the dense inverse of the
+    clover operator, even-odd preconditioned (the inverse odd-site blocks) and
+    on the whole lattice; the preconditioned solve takes fewer iterations."""
     dims, m0, csw, U, Dinv = c2
-    say("clover solve", prec)
     V, N = int(np.prod(dims)), 24
     lat = W.Lattice(dims, -1)
     g = W.Gauge(lat, U)
     g.set_clover(csw)
     b = lat.new_batch(N)
     W.sources(lat, W.source_descs(list(range(N))), b)
-    x = lat.new_batch(N)
-    p = {"fp64": W.FP64, "fp16": W.FP16, "bf16": W.BF16}[prec]
-    tol, bar = (1e-12, 1e-10) if prec == "fp64" else (1e-10, 1e-8)
-    kw = {"inner_tol": 0.05} if prec == "bf16" else {}
-    rc, st = W.solve(g, m0, b, x, N, tol=tol, prec=p, **kw)
-    assert rc == W.OK and all(s["converged"] for s in st)
     E = np.stack([noise.rademacher(s, 12 * V) for s in range(N)], axis=1).astype(complex)
     assert np.array_equal(b.cpu().numpy().reshape(-1, N), E)
     X = Dinv @ E
-    xs = x.cpu().numpy().reshape(-1, N)
-    assert np.max(np.linalg.norm(xs - X, axis=0) / np.linalg.norm(X, axis=0)) < bar
-    full = W.contract(lat, b, x, N).sum(axis=1)
-    ref = np.einsum("ik,ik->k", np.conj(E), X)
-    norms = np.linalg.norm(E, axis=0) * np.linalg.norm(X, axis=0)
-    assert np.all(np.abs(full - ref) <= bar * norms)
+    p = {"fp64": W.FP64, "fp16": W.FP16, "bf16": W.BF16}[prec]
+    tol, bar = (1e-12, 1e-10) if prec == "fp64" else (1e-10, 1e-8)
+    kw = {"inner_tol": 0.05} if prec == "bf16" else {}
+    its = {}
+    try:
+        for eo in (1, 0):
+            say("clover solve", prec, "even-odd", eo)
+            W.set_launch_shape(even_odd=eo)
+            x = lat.new_batch(N)
+            rc, st = W.solve(g, m0, b, x, N, tol=tol, prec=p, **kw)
+            assert rc == W.OK and all(s["converged"] for s in st)
+            its[eo] = max(s["iterations"] for s in st)
+            xs = x.cpu().numpy().reshape(-1, N)
+            assert np.max(np.linalg.norm(xs - X, axis=0) / np.linalg.norm(X, axis=0)) < bar
+            full = W.contract(lat, b, x, N).sum(axis=1)
+            ref = np.einsum("ik,ik->k", np.conj(E), X)
+            norms = np.linalg.norm(E, axis=0) * np.linalg.norm(X, axis=0)
+            assert np.all(np.abs(full - ref) <= bar * norms)
+    finally:
+        W.set_launch_shape()
+    assert its[1] < its[0], its
+
+
+def test_clover_even_odd_mass_change_and_term_change(c2):
+    """The inverse blocks follow m0 and the clover coefficient: solves with a
+    second mass, then a new c_sw, then the first mass again all match their
+    dense inverses."""
+    dims, m0, csw, U, Dinv = c2
+    V, N = int(np.prod(dims)), 6
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    b = lat.new_batch(N)
+    W.sources(lat, W.source_descs([50 + k for k in range(N)]), b)
+    bh = b.cpu().numpy().reshape(-1, N)
+    last = None
+    for mass, c in ((m0, csw), (0.3, csw), (0.3, 0.7), (m0, csw)):
+        say("clover even-odd", mass, c)
+        if c != last:
+            g.set_clover(c)
+            last = c
+        x = lat.new_batch(N)
+        rc, st = W.solve(g, mass, b, x, N, tol=1e-12, prec=W.FP64)
+        assert rc == W.OK and all(s["converged"] for s in st)
+        D = clover.dense_D_clover(U, mass, dims, c)
+        r = bh - D @ x.cpu().numpy().reshape(-1, N)
+        assert np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(bh, axis=0)) <= 1.01e-12
 
 
 def test_clover_batched_next_to_plain_system(c2):
