@@ -836,7 +836,10 @@ __device__ __forceinline__ void dslash_body(const Geom &g, const typename S::lin
             hop_pair<3, DAG, PB, NC, S>(g, U, in, s, nb, r, acc);
             cplx<R> c[12];
             if (cs != R(0)) {
-                load_site<S, NC>(self, s, r, c);
+                // a separate own-term vector is read once: keep it out of the
+                // L2 lines the neighbour gathers reuse
+                if (self.p != in.p) WDT_AUX_LOAD<S, NC>(self, s, r, c);
+                else load_site<S, NC>(self, s, r, c);
                 if constexpr (CLOV == 1)
                     clover_add<R>(Cl + (size_t)s * CLOVER_REALS, c, R(1) / ch, acc);
             } else {

@@ -119,6 +119,8 @@ def main(argv=None):
     ap.add_argument("--eps-link", type=float, default=0.5, help="link spread of the gauge field")
     ap.add_argument("--gauge-seed", type=int, default=2)
     ap.add_argument("--m0", type=float, default=0.02)
+    ap.add_argument("--csw", type=float, default=0.0,
+                    help="clover coefficient (0: the plain Wilson operator)")
     ap.add_argument("--t0", type=int, default=0)
     ap.add_argument("--seeds", type=int, default=8)
     ap.add_argument("--distances", type=int, nargs="*", default=[1, 2, 3, 4])
@@ -139,6 +141,8 @@ def main(argv=None):
     dims = tuple(a.dims)
     lat = wdt.Lattice(dims, -1)
     g = wdt.Gauge(lat, gauge_field(dims, a.eps_link, a.gauge_seed))
+    if a.csw:
+        g.set_clover(a.csw)
     rows = run(g, lat, a.m0, a.t0, range(a.seeds), a.distances, a.dim, a.eps,
                log=lambda s: print(s, flush=True), deflate=a.deflate,
                defl_distances=a.defl_distances, baselines=not a.no_baselines)
@@ -153,7 +157,8 @@ def main(argv=None):
                     solves=len(c["stats"]), seconds=round(time.perf_counter() - t, 3))
         print(json.dumps(dict(connected=conn)), flush=True)
     if a.out:
-        json.dump(dict(dims=list(dims), m0=a.m0, eps_link=a.eps_link, rows=rows, connected=conn),
+        json.dump(dict(dims=list(dims), m0=a.m0, csw=a.csw, eps_link=a.eps_link, rows=rows,
+                       connected=conn),
                   open(a.out, "w"), indent=1)
     return 0
 

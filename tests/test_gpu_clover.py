@@ -276,3 +276,29 @@ def test_clover_full_size_solve_sampled_residual():
     nb = np.linalg.norm(bh.reshape(-1, N), axis=0)
     rel = np.linalg.norm(r.transpose(2, 0, 1).reshape(N, -1), axis=1) / nb
     assert np.max(rel) <= 1.01e-10, np.max(rel)
+
+
+def test_clover_low_modes_match_dense_eigensolver():
+    """The deflation's low modes of Q = Gamma5 D_sw (solves and operator with
+    the clover term) against a dense Hermitian eigensolver of the oracle's
+    Q, with k at a gap of the spectrum."""
+    from oracle import deflation as odfl
+    from paper_2607_05157_amd import deflation
+    dims, m0, csw = (4, 4, 2, 4), -0.6, 1.0
+    U = gauge_field(dims, 0.5, seed=31)
+    D = clover.dense_D_clover(U, m0, dims, csw)
+    Q = odfl.q_matrix(D)
+    lam_all, _ = odfl.low_modes(Q, D.shape[0])
+    a = np.abs(lam_all)
+    k = next(k for k in range(6, 15) if a[k] > 1.03 * a[k - 1])
+    say("clover low modes k", k)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    g.set_clover(csw)
+    lam, Vk, info = deflation.low_modes(g, lat, m0, k, extra=16, tol=1e-9, prec=W.FP64,
+                                        solve_tol=1e-12)
+    assert np.all(info["residuals"] <= 1e-9), info
+    ref_lam, ref_V = odfl.low_modes(Q, k)
+    assert np.max(np.abs(lam - ref_lam) / np.abs(ref_lam)) < 1e-9
+    Vg = Vk.cpu().numpy().reshape(-1, k)
+    assert np.linalg.norm(Vg @ Vg.conj().T - ref_V @ ref_V.conj().T, 2) < 1e-6
