@@ -4,6 +4,8 @@
 #pragma once
 #include "internal.h"
 
+#include <type_traits>
+
 namespace wdt {
 
 struct RhsState {
@@ -145,6 +147,24 @@ __device__ __forceinline__ void scalar_beta_body(RhsState *st, const double2 *pa
 
 template <class S> using Rl = typename S::real;
 
+// Cache policy of the streaming vector kernels: STREAMV loads and stores the
+// vectors non-temporally.  The launches choose it for FP64 vectors larger than
+// the last-level cache (update passes 4.6 -> 5.1-5.2 TB/s on 16^3 x 32,
+// 48 RHS); smaller ones, and the 32-bit-element formats, stay cached (their
+// next pass finds them there: non-temporal, the FP16 passes fell from 4.7 to
+// 4.1-4.2 TB/s).
+template <class S, bool STREAMV>
+__device__ __forceinline__ void vec_load(const SpinorPtr<S> &sp, int site, int r,
+                                         cplx<Rl<S>> (&v)[12]) {
+    if constexpr (STREAMV) load_site_once<S>(sp, site, r, v);
+    else load_site<S>(sp, site, r, v);
+}
+template <class S, bool STREAMV>
+__device__ __forceinline__ void vec_store(const SpinorPtr<S> &sp, int site, int r,
+                                          const cplx<Rl<S>> (&v)[12]) {
+    store_site<S, STREAMV>(sp, site, r, v);
+}
+
 template <class S>
 __device__ __forceinline__ cplx<Rl<S>> to_c(double2 a) {
     return {(Rl<S>)a.x, (Rl<S>)a.y};
@@ -153,7 +173,7 @@ __device__ __forceinline__ cplx<Rl<S>> to_c(double2 a) {
 
 
 // s = r - alpha v
-template <class S>
+template <class S, bool STREAMV = false>
 __device__ __forceinline__ void update_s_body(const Geom &g, int N, int NT, int SB,
                                               const RhsState *__restrict__ st, SpinorPtr<S> rv,
                                               SpinorPtr<S> vv, SpinorPtr<S> sv, int tile, int lb,
@@ -162,16 +182,16 @@ __device__ __forceinline__ void update_s_body(const Geom &g, int N, int NT, int 
     SITE_LOOP_BEGIN_AT(tile, lb, gb)
     const cplx<R> a = to_c<S>(st[r].alpha);
     cplx<R> x[12], y[12];
-    load_site<S>(rv, s, r, x);
-    load_site<S>(vv, s, r, y);
+    vec_load<S, STREAMV>(rv, s, r, x);
+    vec_load<S, STREAMV>(vv, s, r, y);
 #pragma unroll
     for (int k = 0; k < 12; ++k) x[k] = csub(x[k], cmul(a, y[k]));
-    store_site<S>(sv, s, r, x);
+    vec_store<S, STREAMV>(sv, s, r, x);
     SITE_LOOP_END
 }
 
 // x += alpha p + omega s;  r = s - omega t;  partials: rhat^dag r, ||r||^2
-template <class S>
+template <class S, bool STREAMV = false>
 __device__ __forceinline__ void update_xr_body(const Geom &g, int N, int NT, int SB,
                                                const RhsState *__restrict__ st, SpinorPtr<S> xv,
                                                SpinorPtr<S> pv, SpinorPtr<S> sv, SpinorPtr<S> tv,
@@ -184,11 +204,11 @@ __device__ __forceinline__ void update_xr_body(const Geom &g, int N, int NT, int
     const cplx<R> a = to_c<S>(st[r].alpha);
     const cplx<R> w = to_c<S>(st[r].omega);
     cplx<R> x[12], p[12], sv_[12], t[12], h[12];
-    load_site<S>(xv, s, r, x);
-    load_site<S>(pv, s, r, p);
-    load_site<S>(sv, s, r, sv_);
-    load_site<S>(tv, s, r, t);
-    load_site<S>(rhat, s, r, h);
+    vec_load<S, STREAMV>(xv, s, r, x);
+    vec_load<S, STREAMV>(pv, s, r, p);
+    vec_load<S, STREAMV>(sv, s, r, sv_);
+    vec_load<S, STREAMV>(tv, s, r, t);
+    vec_load<S, STREAMV>(rhat, s, r, h);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
         x[k] = cadd(x[k], cadd(cmul(a, p[k]), cmul(w, sv_[k])));
@@ -197,8 +217,8 @@ __device__ __forceinline__ void update_xr_body(const Geom &g, int N, int NT, int
         d0i += (double)h[k].re * p[k].im - (double)h[k].im * p[k].re;
         d1r += (double)p[k].re * p[k].re + (double)p[k].im * p[k].im;
     }
-    store_site<S>(xv, s, r, x);
-    store_site<S>(rv, s, r, p);
+    vec_store<S, STREAMV>(xv, s, r, x);
+    vec_store<S, STREAMV>(rv, s, r, p);
     SITE_LOOP_END
     red[0][tid] = make_double2(d0r, d0i);
     red[1][tid] = make_double2(d1r, 0.0);
@@ -216,7 +236,7 @@ __device__ __forceinline__ void update_xr_body(const Geom &g, int N, int NT, int
 }
 
 // p = r + beta (p - omega v)
-template <class S>
+template <class S, bool STREAMV = false>
 __device__ __forceinline__ void update_p_body(const Geom &g, int N, int NT, int SB,
                                               const RhsState *__restrict__ st, SpinorPtr<S> rv,
                                               SpinorPtr<S> pv, SpinorPtr<S> vv, int tile, int lb,
@@ -226,12 +246,12 @@ __device__ __forceinline__ void update_p_body(const Geom &g, int N, int NT, int 
     const cplx<R> b = to_c<S>(st[r].beta);
     const cplx<R> w = to_c<S>(st[r].omega);
     cplx<R> x[12], p[12], v[12];
-    load_site<S>(rv, s, r, x);
-    load_site<S>(pv, s, r, p);
-    load_site<S>(vv, s, r, v);
+    vec_load<S, STREAMV>(rv, s, r, x);
+    vec_load<S, STREAMV>(pv, s, r, p);
+    vec_load<S, STREAMV>(vv, s, r, v);
 #pragma unroll
     for (int k = 0; k < 12; ++k) p[k] = cadd(x[k], cmul(b, csub(p[k], cmul(w, v[k]))));
-    store_site<S>(pv, s, r, p);
+    vec_store<S, STREAMV>(pv, s, r, p);
     SITE_LOOP_END
 }
 
@@ -329,7 +349,7 @@ __device__ __forceinline__ void scalar_check_body(RhsState *st, const double2 *p
 
 // x += alpha p + omega s;  r = s - omega t;  p = r + beta (p - omega v);
 // partials: ||r||^2
-template <class S>
+template <class S, bool STREAMV = false>
 __device__ __forceinline__ void update_xrp_body(const Geom &g, int N, int NT, int SB,
                                                 const RhsState *__restrict__ st, SpinorPtr<S> xv,
                                                 SpinorPtr<S> pv, SpinorPtr<S> sv, SpinorPtr<S> tv,
@@ -343,11 +363,11 @@ __device__ __forceinline__ void update_xrp_body(const Geom &g, int N, int NT, in
     const cplx<R> w = to_c<S>(st[r].omega);
     const cplx<R> b = to_c<S>(st[r].beta);
     cplx<R> x[12], p[12], sv_[12], t[12], v[12];
-    load_site<S>(xv, s, r, x);
-    load_site<S>(pv, s, r, p);
-    load_site<S>(sv, s, r, sv_);
-    load_site<S>(tv, s, r, t);
-    load_site<S>(vv, s, r, v);
+    vec_load<S, STREAMV>(xv, s, r, x);
+    vec_load<S, STREAMV>(pv, s, r, p);
+    vec_load<S, STREAMV>(sv, s, r, sv_);
+    vec_load<S, STREAMV>(tv, s, r, t);
+    vec_load<S, STREAMV>(vv, s, r, v);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
         x[k] = cadd(x[k], cadd(cmul(a, p[k]), cmul(w, sv_[k])));
@@ -356,9 +376,9 @@ __device__ __forceinline__ void update_xrp_body(const Geom &g, int N, int NT, in
         sv_[k] = rn;
         d0 += (double)rn.re * rn.re + (double)rn.im * rn.im;
     }
-    store_site<S>(xv, s, r, x);
-    store_site<S>(rv, s, r, sv_);
-    store_site<S>(pv, s, r, p);
+    vec_store<S, STREAMV>(xv, s, r, x);
+    vec_store<S, STREAMV>(rv, s, r, sv_);
+    vec_store<S, STREAMV>(pv, s, r, p);
     SITE_LOOP_END
     red[tid] = make_double2(d0, 0.0);
     __syncthreads();

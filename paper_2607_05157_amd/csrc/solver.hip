@@ -57,15 +57,15 @@ __global__ void k_sum_to(double *out, const double2 *partials, int G, int N) {
 
 #define WDT_BLOCK_CTX blockIdx.y, xcd_block(blockIdx.x, gridDim.x), gridDim.x
 
-template <class S>
+template <class S, bool STREAMV = false>
 __global__ __launch_bounds__(256) void k_update_s(Geom g, int N, int NT, int SB,
                                                   const RhsState *__restrict__ st, SpinorPtr<S> rv,
                                                   SpinorPtr<S> vv, SpinorPtr<S> sv,
                                                   const int *live) {
     WDT_LIVE_GUARD
-    update_s_body<S>(g, N, NT, SB, st, rv, vv, sv, WDT_BLOCK_CTX);
+    update_s_body<S, STREAMV>(g, N, NT, SB, st, rv, vv, sv, WDT_BLOCK_CTX);
 }
-template <class S>
+template <class S, bool STREAMV = false>
 __global__ __launch_bounds__(256) void k_update_xr(Geom g, int N, int NT, int SB,
                                                    const RhsState *__restrict__ st, SpinorPtr<S> xv,
                                                    SpinorPtr<S> pv, SpinorPtr<S> sv,
@@ -73,17 +73,17 @@ __global__ __launch_bounds__(256) void k_update_xr(Geom g, int N, int NT, int SB
                                                    SpinorPtr<S> rhat, double2 *partials,
                                                    const int *live) {
     WDT_LIVE_GUARD
-    update_xr_body<S>(g, N, NT, SB, st, xv, pv, sv, tv, rv, rhat, partials, WDT_BLOCK_CTX);
+    update_xr_body<S, STREAMV>(g, N, NT, SB, st, xv, pv, sv, tv, rv, rhat, partials, WDT_BLOCK_CTX);
 }
-template <class S>
+template <class S, bool STREAMV = false>
 __global__ __launch_bounds__(256) void k_update_p(Geom g, int N, int NT, int SB,
                                                   const RhsState *__restrict__ st, SpinorPtr<S> rv,
                                                   SpinorPtr<S> pv, SpinorPtr<S> vv,
                                                   const int *live) {
     WDT_LIVE_GUARD
-    update_p_body<S>(g, N, NT, SB, st, rv, pv, vv, WDT_BLOCK_CTX);
+    update_p_body<S, STREAMV>(g, N, NT, SB, st, rv, pv, vv, WDT_BLOCK_CTX);
 }
-template <class S>
+template <class S, bool STREAMV = false>
 __global__ __launch_bounds__(256) void k_update_xrp(Geom g, int N, int NT, int SB,
                                                     const RhsState *__restrict__ st, SpinorPtr<S> xv,
                                                     SpinorPtr<S> pv, SpinorPtr<S> sv,
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_update_xrp(Geom g, int N, int NT, int S
                                                     SpinorPtr<S> vv, double2 *partials,
                                                     const int *live) {
     WDT_LIVE_GUARD
-    update_xrp_body<S>(g, N, NT, SB, st, xv, pv, sv, tv, rv, vv, partials, WDT_BLOCK_CTX);
+    update_xrp_body<S, STREAMV>(g, N, NT, SB, st, xv, pv, sv, tv, rv, vv, partials, WDT_BLOCK_CTX);
 }
 template <class S>
 __global__ __launch_bounds__(256) void k_norm(Geom g, int N, int NT, int SB, SpinorPtr<S> src,
@@ -504,6 +504,9 @@ int bicgstab_iterate(Bicg &B, int prec, void *x, void *r, void *rhat, void *p, v
                                     "update_xrp_bf16"};
     // the inner solves of the mixed solver take the fused end of iteration
     constexpr bool fused = !std::is_same<S, F64>::value;
+    // FP64 vectors beyond the last-level cache (256 MB of Infinity Cache)
+    // stream past it; smaller ones stay cached for the next pass
+    const bool stream_vecs = !fused && (double)(B.geo.nsites) * N * 12 * 16 > 256.0 * (1 << 20);
     EventGuard ev[2];
     for (auto &e : ev) WDT_HIP(hipEventCreateWithFlags(&e.e, hipEventDisableTiming));
     hipLaunchKernelGGL(k_live, dim3(1), dim3(256), 0, B.stream, B.st, N, B.live, (int *)nullptr);
@@ -514,9 +517,14 @@ int bicgstab_iterate(Bicg &B, int prec, void *x, void *r, void *rhat, void *p, v
         hipLaunchKernelGGL(k_scalar_alpha, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.G, N);
         {
             ProfScope pr(nm_s[prec], 3 * vb, B.stream);
-            hipLaunchKernelGGL((k_update_s<S>), B.grid, dim3(sh.threads), 0, B.stream, B.geo, N, B.NT,
-                               sh.SB, B.st, sp<S>(r, V, N), sp<S>(v, V, N), sp<S>(s, V, N),
-                               (const int *)B.live);
+            if (stream_vecs)
+                hipLaunchKernelGGL((k_update_s<S, true>), B.grid, dim3(sh.threads), 0, B.stream,
+                                   B.geo, N, B.NT, sh.SB, B.st, sp<S>(r, V, N), sp<S>(v, V, N),
+                                   sp<S>(s, V, N), (const int *)B.live);
+            else
+                hipLaunchKernelGGL((k_update_s<S>), B.grid, dim3(sh.threads), 0, B.stream, B.geo,
+                                   N, B.NT, sh.SB, B.st, sp<S>(r, V, N), sp<S>(v, V, N),
+                                   sp<S>(s, V, N), (const int *)B.live);
         }
         if constexpr (fused) {
             WDT_TRY(apply_op(B, prec, EPI_DOT_TSR, s, t, rhat));
@@ -537,18 +545,30 @@ int bicgstab_iterate(Bicg &B, int prec, void *x, void *r, void *rhat, void *p, v
                                N);
             {
                 ProfScope pr(nm_xr[prec], 7 * vb, B.stream);
-                hipLaunchKernelGGL((k_update_xr<S>), B.grid, dim3(sh.threads), 0, B.stream, B.geo,
-                                   N, B.NT, sh.SB, B.st, sp<S>(x, V, N), sp<S>(p, V, N),
-                                   sp<S>(s, V, N), sp<S>(t, V, N), sp<S>(r, V, N),
-                                   sp<S>(rhat, V, N), B.part, (const int *)B.live);
+                if (stream_vecs)
+                    hipLaunchKernelGGL((k_update_xr<S, true>), B.grid, dim3(sh.threads), 0,
+                                       B.stream, B.geo, N, B.NT, sh.SB, B.st, sp<S>(x, V, N),
+                                       sp<S>(p, V, N), sp<S>(s, V, N), sp<S>(t, V, N),
+                                       sp<S>(r, V, N), sp<S>(rhat, V, N), B.part,
+                                       (const int *)B.live);
+                else
+                    hipLaunchKernelGGL((k_update_xr<S>), B.grid, dim3(sh.threads), 0, B.stream,
+                                       B.geo, N, B.NT, sh.SB, B.st, sp<S>(x, V, N), sp<S>(p, V, N),
+                                       sp<S>(s, V, N), sp<S>(t, V, N), sp<S>(r, V, N),
+                                       sp<S>(rhat, V, N), B.part, (const int *)B.live);
             }
             hipLaunchKernelGGL(k_scalar_beta, dim3(N), dim3(256), 0, B.stream, B.st, B.part, sh.Gv,
                                N);
             {
                 ProfScope pr(nm_p[prec], 4 * vb, B.stream);
-                hipLaunchKernelGGL((k_update_p<S>), B.grid, dim3(sh.threads), 0, B.stream, B.geo,
-                                   N, B.NT, sh.SB, B.st, sp<S>(r, V, N), sp<S>(p, V, N),
-                                   sp<S>(v, V, N), (const int *)B.live);
+                if (stream_vecs)
+                    hipLaunchKernelGGL((k_update_p<S, true>), B.grid, dim3(sh.threads), 0,
+                                       B.stream, B.geo, N, B.NT, sh.SB, B.st, sp<S>(r, V, N),
+                                       sp<S>(p, V, N), sp<S>(v, V, N), (const int *)B.live);
+                else
+                    hipLaunchKernelGGL((k_update_p<S>), B.grid, dim3(sh.threads), 0, B.stream,
+                                       B.geo, N, B.NT, sh.SB, B.st, sp<S>(r, V, N),
+                                       sp<S>(p, V, N), sp<S>(v, V, N), (const int *)B.live);
             }
         }
         hipLaunchKernelGGL(k_live, dim3(1), dim3(256), 0, B.stream, B.st, N, B.live,
