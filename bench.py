@@ -37,8 +37,8 @@ HBM_PEAK_GBPS = 8000.0
 # They describe the sources they were taken on and are reported only while
 # those sources are unchanged.
 OPERATOR_SOURCES = ["kernels.h", "device.h", "dslash.hip", "solver.hip", "internal.h"]
-MEASURED_TRAFFIC = {"sources": "d07c787d0c8a7c50",
-                    "dslash_eo_fp16": 1047.7e6, "dslash_hop_fp16": 843.4e6}
+MEASURED_TRAFFIC = {"sources": "11879cf86be1e1ae",
+                    "dslash_eo_fp16": 1047.4e6, "dslash_hop_fp16": 842.5e6}
 
 
 def operator_sources_hash():
@@ -147,7 +147,7 @@ def main():
     ap.add_argument("--bf16-steps", type=int, default=2)
     ap.add_argument("--clover-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--inner-tol", type=float, default=0.005)
+    ap.add_argument("--inner-tol", type=float, default=0.003)
     ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -208,7 +208,7 @@ typedef struct {
     int32_t max_iter;    /* cap on (inner) BiCGStab iterations per RHS */
     int32_t prec;        /* WDT_FP64, WDT_FP32 or WDT_FP16 */
     double inner_tol;    /* relative residual reduction per inner solve
-                            (<= 0: 0.005); the last solve of a RHS stops
+                            (<= 0: 0.003); the last solve of a RHS stops
                             earlier if that already meets tol.  An inner
                             solve also stops after 500 iterations, or for a
                             RHS whose recurrence residual grows 1e4 times past

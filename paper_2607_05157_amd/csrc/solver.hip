@@ -730,7 +730,7 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
     std::vector<RhsState> hs(N);
     std::vector<int> hmask(N);
     std::vector<int> total_it(N, 0), outer(N, 0);
-    const double inner_tol = P.inner_tol > 0 ? P.inner_tol : 5e-3;
+    const double inner_tol = P.inner_tol > 0 ? P.inner_tol : 3e-3;
     const int max_outer = P.max_outer > 0 ? P.max_outer : 30;
     int budget = P.max_iter;
     int rc = WDT_OK;

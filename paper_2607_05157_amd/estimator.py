@@ -69,7 +69,7 @@ def colours_on_slice(dims, n_c, sigma, t0):
 
 
 def probing_loop(gauge, lat, m0, n_c, sigma, t0, seeds, n_rhs=48, dilution=12, tol=1e-10,
-                 prec=wdt.FP16, spin=None, correlator=False, checkpoint=None, inner_tol=0.005,
+                 prec=wdt.FP16, spin=None, correlator=False, checkpoint=None, inner_tol=0.003,
                  max_batches=None, deflation=None):
     """Probing x time dilution x spin-colour dilution estimate of
     tr[B D^-1(t0, t0)] (B = gamma5 by default) and, with correlator=True, of
@@ -154,7 +154,7 @@ def probing_loop(gauge, lat, m0, n_c, sigma, t0, seeds, n_rhs=48, dilution=12, t
 
 
 def connected_correlator(gauge, lat, m0, seeds, t_sources=None, n_rhs=48, tol=1e-10,
-                         prec=wdt.FP16, inner_tol=0.005):
+                         prec=wdt.FP16, inner_tol=0.003):
     """G(t) of eq. connected-results-G with the (1/T) sum over source slices.
 
     For every source slice t' and seed, the 12 spin-colour components of a

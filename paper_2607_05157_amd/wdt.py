@@ -246,7 +246,7 @@ def apply_D(gauge, m0, x, out, n_rhs, prec=FP64, dagger=False, stream=None):
     return out
 
 
-def solve(gauge, m0, b, x, n_rhs, tol=1e-10, prec=FP64, max_iter=10000, inner_tol=0.005,
+def solve(gauge, m0, b, x, n_rhs, tol=1e-10, prec=FP64, max_iter=10000, inner_tol=0.003,
           max_outer=40, x0_is_guess=False, check_every=5, stream=None, allow_unconverged=False):
     p = SolveParams(tol, max_iter, prec, inner_tol, max_outer, int(x0_is_guess), check_every)
     stats = (RhsStats * n_rhs)()
