@@ -421,6 +421,7 @@ __device__ __forceinline__ void norm_body(const Geom &g, int N, int NT, int SB, 
 template <class SS, class SD, bool ADD>
 __device__ __forceinline__ void convert_body(const Geom &g, int N, int NT, int SB,
                                              SpinorPtr<SS> src, SpinorPtr<SD> dst,
+                                             SpinorPtr<SD> dst2,
                                              const double *__restrict__ f,
                                              double2 *__restrict__ partials, int tile, int lb,
                                              int gb) {
@@ -449,6 +450,7 @@ __device__ __forceinline__ void convert_body(const Geom &g, int N, int NT, int S
             d0 += (double)b[k].re * (double)b[k].re + (double)b[k].im * (double)b[k].im;
     }
     store_site<SD>(dst, s, r, b);
+    if (dst2.p) store_site<SD>(dst2, s, r, b);
     SITE_LOOP_END
     if (partials) {
         red[tid] = d0;

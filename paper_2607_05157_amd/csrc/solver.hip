@@ -101,9 +101,10 @@ __global__ __launch_bounds__(256) void k_norm(Geom g, int N, int NT, int SB, Spi
 template <class SS, class SD, bool ADD>
 __global__ __launch_bounds__(256) void k_convert(Geom g, int N, int NT, int SB,
                                                  SpinorPtr<SS> src, SpinorPtr<SD> dst,
+                                                 SpinorPtr<SD> dst2,
                                                  const double *__restrict__ f,
                                                  double2 *__restrict__ partials) {
-    convert_body<SS, SD, ADD>(g, N, NT, SB, src, dst, f, partials, WDT_BLOCK_CTX);
+    convert_body<SS, SD, ADD>(g, N, NT, SB, src, dst, dst2, f, partials, WDT_BLOCK_CTX);
 }
 
 // ---------------------------------------------------------------------------
@@ -801,19 +802,18 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
                                stream));
         WDT_HIP(hipMemsetAsync(e, 0, vbl, stream));
         if (B.eo) {
-            // rS_e = r_e / ||r|| and its norm for the inner state
+            // rS_e = rhat_e = r_e / ||r|| and its norm for the inner state (the
+            // inner iteration reads the even sites only)
             hipLaunchKernelGGL((k_convert<F64, S, false>), grid, dim3(sh.threads), 0, stream, ug,
                                N, NT, sh.SB, sp<F64>(r64, V, N), sp<S>(rS, V, N),
-                               (const double *)fin, B.part);
+                               sp<S>(rhat, V, N), (const double *)fin, B.part);
             hipLaunchKernelGGL(k_init_state, dim3(N), dim3(256), 0, stream, B.st, B.part, sh.Gv,
                                N, inner_tol, (const int *)mask, (const double *)tolr,
                                (const double *)nullptr);
-            WDT_HIP(hipMemcpyAsync(rhat, rS, spinor_bytes(V, N, prec), hipMemcpyDeviceToDevice,
-                                   stream));
         } else {
             // inner system D e = r (low precision), e = 0, rhat = r
             hipLaunchKernelGGL((k_convert<F64, S, false>), grid, dim3(sh.threads), 0, stream, geo,
-                               N, NT, sh.SB, sp<F64>(r64, V, N), sp<S>(rS, V, N),
+                               N, NT, sh.SB, sp<F64>(r64, V, N), sp<S>(rS, V, N), SpinorPtr<S>{},
                                (const double *)fin, (double2 *)nullptr);
             // ||r||^2 in the stored precision: residual of e = 0 against rS
             WDT_TRY(launch_dslash(g, m0, prec, 0, EPI_RESID, e, rhat, rS, N, B.part, sh, stream));
@@ -838,8 +838,8 @@ static int solve_mixed(wdt_gauge_s *g, double m0, const void *b, void *x, int N,
         budget -= done;
         // x += ||r|| e (even-odd: x_e, then x_o from b_o and x_e)
         hipLaunchKernelGGL((k_convert<S, F64, true>), grid, dim3(sh.threads), 0, stream, ug, N, NT,
-                           sh.SB, sp<S>(e, V, N), sp<F64>(x, V, N), (const double *)fout,
-                           (double2 *)nullptr);
+                           sh.SB, sp<S>(e, V, N), sp<F64>(x, V, N), SpinorPtr<F64>{},
+                           (const double *)fout, (double2 *)nullptr);
         WDT_HIP(hipGetLastError());
         if (B.eo) WDT_TRY(schur_odd(B, WDT_FP64, b, x));
     }
