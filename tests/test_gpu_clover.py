@@ -302,3 +302,23 @@ def test_clover_low_modes_match_dense_eigensolver():
     assert np.max(np.abs(lam - ref_lam) / np.abs(ref_lam)) < 1e-9
     Vg = Vk.cpu().numpy().reshape(-1, k)
     assert np.linalg.norm(Vg @ Vg.conj().T - ref_V @ ref_V.conj().T, 2) < 1e-6
+
+
+@pytest.mark.parametrize("N", [1, 64])
+def test_clover_even_odd_rhs_counts(c2, N):
+    """A single RHS and a full 64-lane batch (one site per wavefront at
+    N = 64): mixed FP16 even-odd solves with the clover term against the
+    dense inverse."""
+    dims, m0, csw, U, Dinv = c2
+    say("clover even-odd N", N)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    g.set_clover(csw)
+    b = lat.new_batch(N)
+    W.sources(lat, W.source_descs([200 + k for k in range(N)]), b)
+    x = lat.new_batch(N)
+    rc, st = W.solve(g, m0, b, x, N, tol=1e-10, prec=W.FP16)
+    assert rc == W.OK and all(s["converged"] for s in st)
+    X = Dinv @ b.cpu().numpy().reshape(-1, N)
+    xs = x.cpu().numpy().reshape(-1, N)
+    assert np.max(np.linalg.norm(xs - X, axis=0) / np.linalg.norm(X, axis=0)) < 1e-8
