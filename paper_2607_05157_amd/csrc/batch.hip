@@ -540,6 +540,9 @@ int wdt_batch_solve(wdt_batch b, void *const *dev_b, void *const *dev_x,
         WDT_CHECK(dev_b[i] && dev_x[i] && dev_b[i] != dev_x[i], "wdt_batch_solve: system %d", i);
         b->host[i].vec[V_B] = (double2 *)dev_b[i];
         b->host[i].vec[V_X] = (double2 *)dev_x[i];
+        // the gauge's clover term as it is now (it may have been set, changed
+        // or removed since the plan was made)
+        b->host[i].C = b->gauges[i]->C64;
         b->host[i].eo = (b->gauges[i]->lat.even_odd_ok() && tuning().eo != 0 &&
                          !b->gauges[i]->C64) ? 1 : 0;
     }

@@ -322,3 +322,25 @@ def test_clover_even_odd_rhs_counts(c2, N):
     X = Dinv @ b.cpu().numpy().reshape(-1, N)
     xs = x.cpu().numpy().reshape(-1, N)
     assert np.max(np.linalg.norm(xs - X, axis=0) / np.linalg.norm(X, axis=0)) < 1e-8
+
+
+def test_clover_changed_after_batch_creation(c2):
+    """A batch made before the clover term is set, then solved with it, then
+    after it is removed: each solve uses the gauge's term as it is at that
+    solve (checked against the dense operator of that moment)."""
+    dims, m0, csw, U, Dinv = c2
+    say("clover set after batch creation")
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    N = 4
+    B = W.Batch([g], [m0], [N])
+    b = lat.new_batch(N)
+    W.sources(lat, W.source_descs([300 + k for k in range(N)]), b)
+    bh = b.cpu().numpy().reshape(-1, N)
+    for c in (csw, 0.0):
+        g.set_clover(c)
+        x = lat.new_batch(N)
+        rc, st = B.solve([b], [x], tol=1e-11)
+        assert rc == W.OK and all(t["converged"] for t in st)
+        r = bh - clover.dense_D_clover(U, m0, dims, c) @ x.cpu().numpy().reshape(-1, N)
+        assert np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(bh, axis=0)) <= 1.01e-11, c
