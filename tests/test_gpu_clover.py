@@ -344,3 +344,43 @@ def test_clover_changed_after_batch_creation(c2):
         assert rc == W.OK and all(t["converged"] for t in st)
         r = bh - clover.dense_D_clover(U, m0, dims, c) @ x.cpu().numpy().reshape(-1, N)
         assert np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(bh, axis=0)) <= 1.01e-11, c
+
+
+def test_clover_variance_study_matches_oracle():
+    """The probing-variance study on a clover gauge (mixed FP16 even-odd
+    solves): every estimator's per-seed values against the oracle's estimates
+    from the dense inverse of D_sw with the same noise and colouring."""
+    from oracle import colouring, estimator as oest
+    from paper_2607_05157_amd import study
+    dims, m0, csw, t0, seeds = (4, 4, 4, 4), 0.2, 1.2, 1, [0, 1, 2]
+    say("clover variance study", dims)
+    U = gauge_field(dims, 0.3, seed=39)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    g.set_clover(csw)
+    rows = study.run(g, lat, m0, t0, seeds, distances=(1,), dim=3, eps=0.5, prec=W.FP16,
+                     tol=1e-10)
+    V = int(np.prod(dims))
+    Dinv = osolve.dense_inverse(clover.dense_D_clover(U, m0, dims, csw))
+    for row in rows:
+        if row["distance"] == 0:
+            col, comps = None, ([-1] if row["estimator"] == "hutchinson" else list(range(12)))
+            classes = [0]
+        else:
+            col = colouring.colours(dims, row["sigma"], row["n_c"])
+            comps = list(range(12))
+            classes = sorted(set(col[np.arange(V) // 64 == t0].tolist()))
+        ref = []
+        for s in seeds:
+            tot = 0j
+            for j in classes:
+                for k in comps:
+                    v = noise.probing_vector(dims, s, col, j, k, t0)
+                    if not v.any():
+                        continue
+                    x = (Dinv @ v.ravel()).reshape(V, 12)
+                    tot += oest.sample_dot(v, x, dims, t0, gamma.GAMMA5)
+            ref.append(tot)
+        ref = np.array(ref)
+        got = np.array(row["per_seed_re"]) + 1j * np.array(row["per_seed_im"])
+        assert np.max(np.abs(got - ref)) < 1e-8 * max(1.0, np.max(np.abs(ref))), row["estimator"]
