@@ -384,3 +384,33 @@ def test_clover_variance_study_matches_oracle():
         ref = np.array(ref)
         got = np.array(row["per_seed_re"]) + 1j * np.array(row["per_seed_im"])
         assert np.max(np.abs(got - ref)) < 1e-8 * max(1.0, np.max(np.abs(ref))), row["estimator"]
+
+
+def test_clover_connected_correlator_matches_oracle():
+    """G(t) averaged over source slices on a clover gauge (mixed FP16
+    even-odd solves): per seed against the oracle's norms with the same noise,
+    and the mean within its error of the exact G(t) of D_sw (whose trace form
+    relies on gamma5-hermiticity, which the term keeps)."""
+    from oracle import estimator as oest
+    from paper_2607_05157_amd import estimator as E
+    dims, m0, csw, seeds = (4, 4, 2, 6), 0.2, 1.3, [0, 1, 2]
+    say("clover connected correlator", dims)
+    U = gauge_field(dims, 0.4, seed=40)
+    lat = W.Lattice(dims, -1)
+    g = W.Gauge(lat, U)
+    g.set_clover(csw)
+    out = E.connected_correlator(g, lat, m0, seeds, n_rhs=48, tol=1e-10, prec=W.FP16)
+    V, T = int(np.prod(dims)), dims[3]
+    Dinv = osolve.dense_inverse(clover.dense_D_clover(U, m0, dims, csw))
+    ref = np.zeros((len(seeds), T))
+    for a, s in enumerate(seeds):
+        for tp in range(T):
+            for k in range(12):
+                v = noise.probing_vector(dims, s, None, None, k, tp)
+                x = (Dinv @ v.ravel()).reshape(V, 12)
+                ref[a] += np.roll(oest.sample_norm2_per_t(x, dims), -tp)
+    ref /= T
+    assert np.max(np.abs(out["per_seed"] - ref)) < 1e-8 * np.max(ref)
+    exact = np.array([oest.exact_G(Dinv, dims, t).real for t in range(T)])
+    err = np.sqrt(out["var"] / len(seeds))
+    assert np.all(np.abs(out["G"] - exact) < 6 * err + 1e-8 * exact)
