@@ -112,8 +112,9 @@ int wdt_gauge_get(wdt_gauge g, double *host_links);
  * F = (Q - Q^dag) / (8i), Q_{mu nu}(x) the sum of the four plaquettes of the
  * (mu, nu) plane that start and end at x in the same sense (periodic in every
  * direction; the fermion time-boundary factor is not part of these loops; F
- * keeps its colour trace).  C is Hermitian and commutes with gamma5, so
- * D^dag = gamma5 D gamma5 still holds.
+ * keeps its colour trace).  The sign is the one with which csw = 1 cancels
+ * the Wilson term's O(a) shift at tree level.  C is Hermitian and commutes
+ * with gamma5, so D^dag = gamma5 D gamma5 still holds.
  *
  * wdt_gauge_set_clover builds C from the FP64 links (FP64, plus an FP32 copy
  * for the FP32 / FP16 / BF16 operators: 72 * 12 bytes per site of device
@@ -122,10 +123,13 @@ int wdt_gauge_get(wdt_gauge g, double *host_links);
  * on the odd sites, computed on the solve's stream at the first solve with a
  * given m0 and kept with the gauge (another 72 * 12 bytes per site); solves
  * on one gauge with different m0 must therefore not run concurrently.  The
- * batched solver takes clover systems without even-odd preconditioning.
- * wdt_force returns WDT_EINVAL while a term is set (its derivative is not
- * implemented).
- * WDT_EINVAL for a null handle or a non-finite csw.
+ * batched solver takes each gauge's term as it is at every wdt_batch_solve
+ * (set, changed or removed after wdt_batch_create) and solves clover systems
+ * without even-odd preconditioning.  wdt_force returns WDT_EINVAL while a
+ * term is set (its derivative is not implemented).
+ * WDT_EINVAL for a null handle or a non-finite csw; WDT_ENOMEM when the
+ * device memory cannot be allocated (the gauge keeps its previous term; its
+ * inverse blocks are recomputed at the next even-odd solve).
  *
  * wdt_gauge_get_clover copies C to host_packed (host, V * 72 doubles): per
  * site the two chiral 6 x 6 blocks (spins 0-1, then 2-3; index 3 * spin +
